@@ -1,0 +1,288 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each test checks the oracle against something other than itself: a closed
+form, an exact identity of the 1/r energy (Eq. 2), a finite difference taken
+through a different code path, a circulant spectrum, or brute-force minima.
+A plausible slip in the oracle (a dropped term, a sign, a transposed index, a
+missing factor 1/2 in the subdomain objective of Eqs. 6-7) fails one of them.
+"""
+import json
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_24722_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def ngon(n, phase=0.3):
+    t = phase + 2.0 * np.pi * np.arange(n) / n
+    return np.cos(t), np.sin(t)
+
+
+def ngon_energy_closed(n):
+    """Regular n-gon on the unit circle: E = (n/2) sum_k 1/(2 sin(pi k/n))."""
+    mpmath.mp.dps = 40
+    return float(mpmath.mpf(n) / 2 * mpmath.fsum(1 / (2 * mpmath.sin(mpmath.pi * k / n)) for k in range(1, n)))
+
+
+def random_config(n, seed):
+    return W.uniform_disk(n, seed)
+
+
+@pytest.mark.parametrize("n", list(range(2, 14)) + [50, 97])
+def test_ngon_energy_closed_form(n):
+    x, y = ngon(n)
+    E = O.energy(x, y)
+    assert abs(E - ngon_energy_closed(n)) <= 4e-16 * n * ngon_energy_closed(n)
+
+
+@pytest.mark.parametrize("n", [3, 7, 12, 40])
+def test_ngon_forces_radial_euler(n):
+    # By symmetry every force is radial; by Euler (E homogeneous of degree -1)
+    # sum_i r_i . F_i = E, so each charge carries E_n / n outward.
+    x, y = ngon(n)
+    fx, fy = O.forces(x, y)
+    En = ngon_energy_closed(n)
+    radial = fx * x + fy * y
+    tangential = -fx * y + fy * x
+    np.testing.assert_allclose(radial, En / n, rtol=1e-13)
+    assert np.max(np.abs(tangential)) <= 1e-13 * En / n
+
+
+def test_local_energies_sum_and_ngon():
+    x, y = random_config(300, 7)
+    E, e = O.energy(x, y, local=True)
+    assert abs(e.sum() - E) <= 1e-13 * E
+    xn, yn = ngon(9)
+    _, en = O.energy(xn, yn, local=True)
+    np.testing.assert_allclose(en, ngon_energy_closed(9) / 9, rtol=1e-14)
+
+
+def test_euler_identity_random():
+    x, y = random_config(500, 11)
+    E = O.energy(x, y)
+    fx, fy = O.forces(x, y)
+    assert abs(np.sum(x * fx + y * fy) - E) <= 1e-12 * E
+
+
+def test_newton_third_law():
+    x, y = random_config(400, 12)
+    fx, fy = O.forces(x, y)
+    scale = np.sum(np.abs(fx)) + np.sum(np.abs(fy))
+    assert abs(fx.sum()) <= 1e-13 * scale and abs(fy.sum()) <= 1e-13 * scale
+
+
+def test_hessian_homogeneity():
+    # grad E homogeneous of degree -2  =>  H r = 2 F
+    x, y = random_config(300, 13)
+    fx, fy = O.forces(x, y)
+    hx, hy = O.hvp(x, y, x, y)
+    err = np.sqrt(np.sum((hx - 2 * fx) ** 2 + (hy - 2 * fy) ** 2) / np.sum(4 * (fx ** 2 + fy ** 2)))
+    assert err <= 1e-12
+
+
+def test_rotation_identities():
+    x, y = random_config(250, 14)
+    th = 0.7
+    c, s = np.cos(th), np.sin(th)
+    xr, yr = c * x - s * y, s * x + c * y
+    assert abs(O.energy(xr, yr) - O.energy(x, y)) <= 1e-13 * O.energy(x, y)
+    fx, fy = O.forces(x, y)
+    frx, fry = O.forces(xr, yr)
+    scale = np.sqrt(np.mean(fx ** 2 + fy ** 2))
+    assert np.max(np.abs(frx - (c * fx - s * fy))) <= 1e-12 * scale
+    assert np.max(np.abs(fry - (s * fx + c * fy))) <= 1e-12 * scale
+    # d/dtheta of grad E(R r) = R grad E(r) at 0:  H (J r) = J grad E = -J F
+    hx, hy = O.hvp(x, y, -y, x)
+    np.testing.assert_allclose(hx, fy, atol=1e-11 * scale)
+    np.testing.assert_allclose(hy, -fx, atol=1e-11 * scale)
+
+
+def test_translation_mode_and_permutation():
+    x, y = random_config(200, 15)
+    hx, hy = O.hvp(x, y, np.ones_like(x), np.zeros_like(x))
+    assert np.max(np.abs(hx)) == 0.0 and np.max(np.abs(hy)) == 0.0
+    p = np.random.default_rng(3).permutation(x.size)
+    assert abs(O.energy(x[p], y[p]) - O.energy(x, y)) <= 1e-13 * O.energy(x, y)
+    fx, fy = O.forces(x, y)
+    fpx, fpy = O.forces(x[p], y[p])
+    np.testing.assert_allclose(fpx, fx[p], rtol=1e-12, atol=1e-12 * np.abs(fx).max())
+
+
+def test_forces_vs_energy_differences():
+    # Central differences of E through orc_esub_delta (a different code path:
+    # differences of 1/r over the changed pairs), one charge moved at a time.
+    x, y = random_config(400, 16)
+    fx, fy = O.forces(x, y)
+    h = O.spacing(x.size)
+    eps = 1e-6 * h
+    for k in [0, 17, 123, 399]:
+        idx = np.array([k], dtype=np.int32)
+        for comp, f in ((0, fx[k]), (1, fy[k])):
+            dp = np.array([x[k], y[k]])
+            dm = dp.copy()
+            dp[comp] += eps
+            dm[comp] -= eps
+            Ep = O.esub_delta(x, y, idx, dp[:1], dp[1:])
+            Em = O.esub_delta(x, y, idx, dm[:1], dm[1:])
+            fd = -(Ep - Em) / (2 * eps)
+            assert abs(fd - f) <= 1e-7 * max(abs(f), 1.0 / h ** 2)
+
+
+def test_hvp_vs_force_differences_and_dense():
+    x, y = random_config(150, 17)
+    vx, vy = W.unit_vector(x.size, 5)
+    hx, hy = O.hvp(x, y, vx, vy)
+    eps = 1e-6
+    fpx, fpy = O.forces(x + eps * vx, y + eps * vy)
+    fmx, fmy = O.forces(x - eps * vx, y - eps * vy)
+    gx = -(fpx - fmx) / (2 * eps)
+    gy = -(fpy - fmy) / (2 * eps)
+    norm = np.sqrt(np.sum(hx ** 2 + hy ** 2))
+    assert np.sqrt(np.sum((gx - hx) ** 2 + (gy - hy) ** 2)) <= 1e-6 * norm
+    H = O.hessian(x, y)
+    assert np.max(np.abs(H - H.T)) <= 1e-12 * np.max(np.abs(H))
+    v = np.empty(2 * x.size)
+    v[0::2] = vx
+    v[1::2] = vy
+    Hv = H @ v
+    assert np.sqrt(np.sum((Hv[0::2] - hx) ** 2 + (Hv[1::2] - hy) ** 2)) <= 1e-12 * norm
+
+
+def test_esub_is_total_minus_frozen():
+    # Eqs. 6-7 (reading: 1/2 on active-active pairs): E_sub(A) = E(all) - E(F).
+    x, y = random_config(400, 18)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(x.size, 60, replace=False)).astype(np.int32)
+    frozen = np.setdiff1d(np.arange(x.size), idx)
+    Esub, gx, gy = O.esub(x, y, idx, grad=True)
+    Eall = O.energy(x, y)
+    Ef = O.energy(x[frozen], y[frozen])
+    assert abs(Esub - (Eall - Ef)) <= 1e-13 * Eall
+    fx, fy = O.forces(x, y)
+    np.testing.assert_allclose(gx, -fx[idx], rtol=1e-12, atol=1e-12 * np.abs(fx).max())
+    np.testing.assert_allclose(gy, -fy[idx], rtol=1e-12, atol=1e-12 * np.abs(fy).max())
+    # the local energies of the active charges sum to E_sub minus the
+    # active-frozen half that e_i counts once
+    E2, e = O.energy(x, y, local=True)
+    aa = O.energy(x[idx], y[idx])
+    assert abs(e[idx].sum() - (Esub - 0.5 * (Esub - aa))) <= 1e-12 * Eall
+
+
+def test_esub_delta_matches_total_energy_change():
+    x, y = random_config(400, 19)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(x.size, 40, replace=False)).astype(np.int32)
+    h = O.spacing(x.size)
+    for scale in (1e-3, 0.3):
+        xa = x[idx] + rng.normal(0, scale * h, idx.size)
+        ya = y[idx] + rng.normal(0, scale * h, idx.size)
+        X, Y = x.copy(), y.copy()
+        X[idx], Y[idx] = xa, ya
+        d = O.esub_delta(x, y, idx, xa, ya)
+        dtot = O.energy(X, Y) - O.energy(x, y)
+        dsub = O.esub(x, y, idx, xa, ya) - O.esub(x, y, idx)
+        tol = 1e-14 * O.energy(x, y) * 4
+        assert abs(d - dtot) <= tol and abs(d - dsub) <= tol
+
+
+def test_esub_hvp_vs_gradient_differences():
+    x, y = random_config(300, 20)
+    rng = np.random.default_rng(2)
+    idx = np.sort(rng.choice(x.size, 50, replace=False)).astype(np.int32)
+    vx, vy = W.unit_vector(idx.size, 9)
+    hx, hy = O.esub_hvp(x, y, idx, None, None, vx, vy)
+    eps = 1e-6
+    _, gpx, gpy = O.esub(x, y, idx, x[idx] + eps * vx, y[idx] + eps * vy, grad=True)
+    _, gmx, gmy = O.esub(x, y, idx, x[idx] - eps * vx, y[idx] - eps * vy, grad=True)
+    fdx = (gpx - gmx) / (2 * eps)
+    fdy = (gpy - gmy) / (2 * eps)
+    norm = np.sqrt(np.sum(hx ** 2 + hy ** 2))
+    assert np.sqrt(np.sum((fdx - hx) ** 2 + (fdy - hy) ** 2)) <= 1e-6 * norm
+
+
+def test_reduce_grad_wall_rule():
+    # n-gon: every charge is on the wall, pushed outward -> held, and the
+    # reduced gradient (tangential force) vanishes.
+    x, y = ngon(10)
+    fx, fy = O.forces(x, y)
+    tx, ty, held, m = O.reduce_grad(x, y, -fx, -fy)
+    assert held.all() and m <= 1e-13 * np.abs(fx).max()
+    # a charge inside the disk is never held; one on the wall pulled inward is free
+    tx, ty, held, m = O.reduce_grad(np.array([0.5, 1.0]), np.array([0.0, 0.0]),
+                                    np.array([-3.0, 2.0]), np.array([1.0, 1.0]))
+    assert list(held) == [0, 0] and m == 3.0
+    tx, ty, held, m = O.reduce_grad(np.array([1.0]), np.array([0.0]), np.array([-3.0]), np.array([1.0]))
+    assert list(held) == [1] and m == 1.0 and tx[0] == 0.0
+
+
+@pytest.mark.parametrize("n", [5, 11])
+def test_ngon_tangent_spectrum(n):
+    # Angular Hessian of a ring is circulant: lambda_m = sum_k f''(2 pi k/n)
+    # (1 - cos(2 pi k m/n)), f(t) = 1/(2 sin(t/2)), f'' = (1 + cos^2(t/2))/(8 sin^3(t/2)).
+    x, y = ngon(n)
+    Hr, Q = O.tangent_hessian_dense(x, y)
+    assert Hr.shape == (n, n)
+    ev = np.sort(np.linalg.eigvalsh(Hr))
+    k = np.arange(1, n)
+    t = 2 * np.pi * k / n
+    fpp = (1 + np.cos(t / 2) ** 2) / (8 * np.sin(t / 2) ** 3)
+    lam = np.sort([np.sum(fpp * (1 - np.cos(2 * np.pi * k * m / n))) for m in range(n)])
+    np.testing.assert_allclose(ev, lam, atol=1e-12 * lam.max())
+
+
+def test_bruteforce_small_minima():
+    # Multi-start relax; for n <= 11 the lowest minimum found is the regular
+    # n-gon, for n = 12 an 11-ring plus a centre charge (E_11 + 11), which is
+    # below the 12-gon.
+    for n in range(2, 13):
+        best = np.inf
+        for s in range(120):
+            x, y = W.uniform_disk(n, 50000 + 1000 * n + s)
+            xa, ya, st = O.relax(x, y, np.arange(n), gtol=1e-12, max_iter=4000)
+            if st["status"] == 0:
+                best = min(best, O.energy(xa, ya))
+        target = ngon_energy_closed(n) if n <= 11 else ngon_energy_closed(11) + 11.0
+        assert abs(best - target) <= 1e-13 * target, (n, best, target)
+    assert ngon_energy_closed(11) + 11.0 < ngon_energy_closed(12)
+
+
+def test_relax_uniform_start_kkt_and_band():
+    # Full relax of 300 uniform charges: reduced gradient below 1e-10, every
+    # held charge pushed outward, the tangent Hessian positive apart from the
+    # exact rotation mode, and the energy just above the asymptotic expansion.
+    n = 300
+    x, y = W.uniform_disk(n, 1001)
+    xa, ya, st = O.relax(x, y, np.arange(n), gtol=1e-10)
+    assert st["status"] == 0 and st["gtan_inf"] <= 1e-10
+    fx, fy = O.forces(xa, ya)
+    tx, ty, held, m = O.reduce_grad(xa, ya, -fx, -fy)
+    assert m <= 1e-10
+    assert np.all((fx * xa + fy * ya)[held == 1] > 0)
+    Hr, Q = O.tangent_hessian_dense(xa, ya)
+    ev, vec = np.linalg.eigh(Hr)
+    # lowest mode: the exact rigid rotation (zero eigenvalue); the rest positive
+    rot = Q.T @ np.stack([-ya, xa], axis=1).ravel()
+    rot /= np.linalg.norm(rot)
+    assert abs(ev[0]) <= 1e-9 * ev[-1] and abs(vec[:, 0] @ rot) >= 1 - 1e-6
+    assert ev[1] > 1e6 * abs(ev[0]) and ev[1] > 1e-7 * ev[-1]
+    g = json.load(open(os.path.join(GOLD, "asymptotic.json")))
+    Ea = np.pi / 4 * n ** 2 + g["k2"] * n ** 1.5 + g["k3"] * n + g["k4"] * n ** 0.5 + g["k5"]
+    E = O.energy(xa, ya)
+    assert 0.0 <= (E - Ea) / Ea <= 2e-3
+
+
+def test_asymptotic_expansion_golden():
+    # The coefficients quoted in the paper reproduce its printed extrapolation
+    # and deviation (Eq. 1 and Eq. 11), which pins the band used above.
+    g = json.load(open(os.path.join(GOLD, "asymptotic.json")))
+    n = g["N"]
+    Ea = np.pi / 4 * n ** 2 + g["k2"] * n ** 1.5 + g["k3"] * n + g["k4"] * n ** 0.5 + g["k5"]
+    assert abs(Ea - g["E_asym_printed"]) <= 5e-13 * Ea
+    dev = abs(g["E_min_printed"] - Ea) / Ea
+    assert abs(dev - g["deviation_printed"]) <= 5e-10
