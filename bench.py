@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-pairs energy+force pass on one MI355X.
+
+One step = one coulomb_forces call (energy fused with forces, mixed precision:
+FP32 pairs, FP64 folds) on N = 100 000 charges of the warped-lattice workload
+(sigma = 0.02 h), inputs resident in HBM before the timed region.  The metric
+counts ordered pair interactions, N(N-1) per call.
+
+Printed: one JSON line with the driver's fields plus
+  roofline      the symmetric pair kernel against the FP32 vector peak
+                (algorithmic flops: 13 per ordered pair; kernel time from HIP
+                events recorded around that kernel on its stream);
+  cpu_baseline  the CPU oracle on a bounded sample of rows of the same input;
+  extra         FP64 energy+forces, HVP (both precisions) and energy-only rates.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak
+FLOPS_EF = 13                # energy+forces: 2 sub, 3 r^2, 1 rsqrt, 1 add, 2 r^-3, 4 FMA
+FLOPS_HVP = 24
+
+
+def hip_runtime():
+    import torch
+    path = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    h = ctypes.CDLL(path if os.path.exists(path) else "libamdhip64.so.7")
+    h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    h.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return h
+
+
+def timed(fn, steps, warmup, lib, hip):
+    """Run fn warmup+steps times; returns (ms per call over the region, mean
+    ms of the dominant pair kernel from events recorded around it)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(steps):
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        hip.hipEventCreate(ctypes.byref(a))
+        hip.hipEventCreate(ctypes.byref(b))
+        evs.append((a, b))
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for a, b in evs:
+        lib.coulomb_set_kernel_events(a, b)
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    lib.coulomb_set_kernel_events(None, None)
+    region_ms = t0.elapsed_time(t1) / steps
+    ks = []
+    for a, b in evs:
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), a, b)
+        ks.append(ms.value)
+        hip.hipEventDestroy(a)
+        hip.hipEventDestroy(b)
+    return region_ms, sum(ks) / len(ks)
+
+
+def cpu_baseline(x, y, seconds=15.0):
+    """The oracle's E+F sums on a bounded sample of rows of the same input."""
+    import numpy as np
+    import oracle as O
+    n = x.size
+    rows = np.arange(0, n, max(1, n // 200), dtype=np.int32)
+    t = time.perf_counter()
+    O.rows(x, y, rows)
+    dt = time.perf_counter() - t
+    rate = rows.size * (n - 1) / dt
+    m = int(min(n, max(rows.size, seconds * rate / (n - 1))))
+    rows = np.linspace(0, n - 1, m).astype(np.int32)
+    t = time.perf_counter()
+    O.rows(x, y, rows)
+    dt = time.perf_counter() - t
+    return {"value": rows.size * (n - 1) / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{rows.size} of {n} charges (rows spread evenly), each against all {n - 1} others: "
+                      f"FP64 Neumaier sums of 1/r and (r_i - r_j)/r^3, {dt:.1f} s"}
+
+
+def traffic_from_profiles():
+    """HBM bytes per launch of the pair kernel from the committed counter
+    summary, if it matches the current kernel build; else None."""
+    p = os.path.join(ROOT, "profiles", "k_sym_forces_n100000_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        src = open(os.path.join(ROOT, "paper_2609_24722_amd", "csrc", "pairs.hip"), "rb").read()
+        import hashlib
+        if d.get("pairs_hip_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return d.get("traffic_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the all-pairs pass shards by i-range across GPUs "
+              "(design in DESIGN.md) but no multi-GPU path is built; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_24722_amd import FP64, MIXED, ops, workloads as W
+
+    dev = torch.device("cuda:0")
+    lib = ops.lib()
+    lib.coulomb_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.coulomb_set_kernel_events.restype = None
+    hip = hip_runtime()
+
+    x, y = W.workload(3, args.n)
+    n = x.size
+    pairs = n * (n - 1)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+    vx, vy = W.unit_vector(n, 1103)
+    vxt = torch.tensor(vx, device=dev)
+    vyt = torch.tensor(vy, device=dev)
+    torch.cuda.synchronize()
+
+    step_ms, kern_ms = timed(lambda: ops.forces(xt, yt, MIXED), args.steps, args.warmup, lib, hip)
+    value = pairs / (step_ms * 1e-3)
+    achieved = FLOPS_EF * pairs / (kern_ms * 1e-3) / 1e12
+    out = {
+        "metric": "pair-interactions/s (E+F, N=1e5)",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"N={n} charges, warped triangular lattice with Gaussian jitter 0.02 h "
+                        f"(seed 1003); one fused energy+force evaluation, FP32 pairs on block-relative "
+                        f"coordinates folded into FP64",
+            "n": n,
+            "pairs_per_step": pairs,
+            "pair_convention": "ordered, N(N-1); each unordered pair is evaluated once",
+            "precision": "mixed",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": traffic_from_profiles(),
+            "kernel": "cd::k_sym<1,false> (energy+forces)",
+            "kernel_ms": kern_ms,
+            "flops_per_pair": FLOPS_EF,
+        },
+    }
+    if not args.no_extra:
+        extra = {}
+        s, k = timed(lambda: ops.forces(xt, yt, FP64), 3, 1, lib, hip)
+        extra["fp64_forces"] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k,
+                                "alg_tflops": FLOPS_EF * pairs / (k * 1e-3) / 1e12}
+        for name, prec in (("mixed_hvp", MIXED), ("fp64_hvp", FP64)):
+            s, k = timed(lambda: ops.hvp(xt, yt, vxt, vyt, prec), 5 if prec == MIXED else 3, 1, lib, hip)
+            extra[name] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k,
+                           "alg_tflops": FLOPS_HVP * pairs / (k * 1e-3) / 1e12}
+        s, k = timed(lambda: ops.energy(xt, yt, MIXED), 5, 1, lib, hip)
+        extra["mixed_energy"] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k}
+        out["extra"] = extra
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(x, y)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

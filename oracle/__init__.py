@@ -89,6 +89,8 @@ def lib():
         L.orc_relax.restype = None
         L.orc_relax.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _D, _D,
                                 ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
+        L.orc_rows.restype = None
+        L.orc_rows.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int64, _I32, _D, _D, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -146,6 +148,23 @@ def hvp(x, y, vx, vy):
     hy = np.empty(x.size)
     lib().orc_hvp(x.size, px, py, pvx, pvy, hx.ctypes.data_as(_D), hy.ctypes.data_as(_D))
     return hx, hy
+
+
+def rows(x, y, rows, vx=None, vy=None):
+    """F_i (or (H v)_i if v is given) and e_i for the charges in ``rows``."""
+    x, px = _d(x)
+    y, py = _d(y)
+    rows, pr = _i(rows)
+    pvx = pvy = None
+    if vx is not None:
+        vx, pvx = _d(vx)
+        vy, pvy = _d(vy)
+    o0 = np.empty(rows.size)
+    o1 = np.empty(rows.size)
+    e = np.empty(rows.size)
+    lib().orc_rows(x.size, px, py, pvx, pvy, rows.size, pr, o0.ctypes.data_as(_D),
+                   o1.ctypes.data_as(_D), e.ctypes.data_as(_D))
+    return o0, o1, e
 
 
 def hessian(x, y):

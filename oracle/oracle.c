@@ -22,6 +22,7 @@
  *   orc_hvp          Hessian-vector product of Eq. 2: second derivatives of
  *                    1/|d| are (3 d d^T - |d|^2 I)/|d|^5.
  *   orc_hessian      the same Hessian as a dense 2N x 2N matrix (tiny N).
+ *   orc_rows         forces, HVP rows and e_i for a subset of charges.
  *   orc_esub         subdomain objective of Eqs. 6-7 with the reading
  *                    E_sub = sum_{i in A} e_i, e_i = 1/2 sum_{j in A, j!=i}
  *                    1/r_ij + sum_{j in F} 1/r_ij, and its gradient over A.
@@ -120,6 +121,38 @@ void orc_forces(int64_t n, const double *x, const double *y, double *fx, double 
     }
     fx[i] = nval(&ax);
     fy[i] = nval(&ay);
+  }
+}
+
+/* The same sums for a subset of rows only (sampled checks at large N):
+ * out0/out1 = F_i, or (H v)_i when vx != NULL; e_out = e_i (nullable). */
+void orc_rows(int64_t n, const double *x, const double *y, const double *vx, const double *vy,
+              int64_t nrows, const int32_t *rows, double *out0, double *out1, double *e_out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    nacc a0 = {0, 0}, a1 = {0, 0}, ae = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dx = x[i] - x[j], dy = y[i] - y[j];
+      double r2 = dx * dx + dy * dy;
+      double rr = sqrt(r2);
+      nadd(&ae, 1.0 / rr);
+      double i3 = 1.0 / (r2 * rr);
+      if (vx) {
+        double wx = vx[i] - vx[j], wy = vy[i] - vy[j];
+        double i5 = i3 / r2;
+        double dw = dx * wx + dy * wy;
+        nadd(&a0, 3.0 * dx * dw * i5 - wx * i3);
+        nadd(&a1, 3.0 * dy * dw * i5 - wy * i3);
+      } else {
+        nadd(&a0, dx * i3);
+        nadd(&a1, dy * i3);
+      }
+    }
+    if (out0) out0[r] = nval(&a0);
+    if (out1) out1[r] = nval(&a1);
+    if (e_out) e_out[r] = 0.5 * nval(&ae);
   }
 }
 

@@ -1,0 +1,148 @@
+"""ctypes binding of libcoulombdisk.so: argument marshalling only.
+
+Every function takes torch tensors that live on a GPU (float64, contiguous,
+same device), sizes the library's scratch from ``coulomb_workspace_bytes``,
+and enqueues on torch's current stream.  No computation happens here; if the
+shared library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import FP64, MIXED
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoulombdisk.so")
+
+OP_ENERGY, OP_FORCES, OP_HVP, OP_VALIDATE, OP_PATCHES, OP_RELAX, OP_LANCZOS = range(7)
+
+_lib = None
+_ws = {}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+
+
+class CoulombError(RuntimeError):
+    pass
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CoulombError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.coulomb_workspace_bytes.restype = _sz
+        L.coulomb_workspace_bytes.argtypes = [ctypes.c_int, _i64, _i32, _i64, ctypes.c_int]
+        L.coulomb_energy.restype = ctypes.c_int
+        L.coulomb_energy.argtypes = [_vp, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]
+        L.coulomb_forces.restype = ctypes.c_int
+        L.coulomb_forces.argtypes = [_vp, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.coulomb_hvp.restype = ctypes.c_int
+        L.coulomb_hvp.argtypes = [_vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]
+        L.coulomb_validate.restype = ctypes.c_int
+        L.coulomb_validate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp]
+        L.coulomb_status_string.restype = ctypes.c_char_p
+        L.coulomb_status_string.argtypes = [ctypes.c_int]
+        _bind_relax(L)
+        _lib = L
+    return _lib
+
+
+def _bind_relax(L):
+    if hasattr(L, "relax_subdomains"):
+        from . import relax as _r  # noqa: F401  (binds its own symbols)
+        _r._bind(L)
+
+
+def check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise CoulombError(f"{what}: {lib().coulomb_status_string(rc).decode()} ({rc})")
+
+
+def workspace(op: int, n: int, precision: int, device, n_patches: int = 0, total_active: int = 0):
+    """Device scratch for ``op`` (grown on demand, cached per device and op)."""
+    nbytes = int(lib().coulomb_workspace_bytes(op, n, n_patches, total_active, precision))
+    if nbytes == 0:
+        raise CoulombError(f"invalid sizes for op {op}: n={n}")
+    key = (str(device), op)
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _ws[key] = buf
+    return buf, nbytes
+
+
+def stream_ptr(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _chk(*ts):
+    dev = ts[0].device
+    if dev.type != "cuda":
+        raise CoulombError("tensors must live on a GPU")
+    for t in ts:
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != dev:
+            raise CoulombError("expected contiguous float64 tensors on one device")
+        if t.numel() != ts[0].numel():
+            raise CoulombError("length mismatch")
+    return dev
+
+
+def energy(x, y, precision: int = MIXED, local: bool = False):
+    """E = sum_{i<j} 1/r_ij (Eq. 2) as a 1-element tensor; with local=True
+    also e_i = 1/2 sum_{j!=i} 1/r_ij (Sec. II.C step 1)."""
+    dev = _chk(x, y)
+    n = x.numel()
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    e = torch.empty(n, dtype=torch.float64, device=dev) if local else None
+    ws, nb = workspace(OP_ENERGY, n, precision, dev)
+    check(lib().coulomb_energy(x.data_ptr(), y.data_ptr(), n, precision, E.data_ptr(),
+                               e.data_ptr() if local else None, ws.data_ptr(), nb, stream_ptr(dev)),
+          "coulomb_energy")
+    return (E, e) if local else E
+
+
+def forces(x, y, precision: int = MIXED, with_energy: bool = True):
+    """F_i = -dE/dr_i; returns (fx, fy, E or None)."""
+    dev = _chk(x, y)
+    n = x.numel()
+    fx = torch.empty(n, dtype=torch.float64, device=dev)
+    fy = torch.empty(n, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev) if with_energy else None
+    ws, nb = workspace(OP_FORCES, n, precision, dev)
+    check(lib().coulomb_forces(x.data_ptr(), y.data_ptr(), n, precision, fx.data_ptr(), fy.data_ptr(),
+                               E.data_ptr() if with_energy else None, ws.data_ptr(), nb,
+                               stream_ptr(dev)), "coulomb_forces")
+    return fx, fy, E
+
+
+def hvp(x, y, vx, vy, precision: int = MIXED):
+    """(H v)_i = sum_{j!=i} K(d_ij)(v_i - v_j); returns (hx, hy)."""
+    dev = _chk(x, y, vx, vy)
+    n = x.numel()
+    hx = torch.empty(n, dtype=torch.float64, device=dev)
+    hy = torch.empty(n, dtype=torch.float64, device=dev)
+    ws, nb = workspace(OP_HVP, n, precision, dev)
+    check(lib().coulomb_hvp(x.data_ptr(), y.data_ptr(), vx.data_ptr(), vy.data_ptr(), n, precision,
+                            hx.data_ptr(), hy.data_ptr(), ws.data_ptr(), nb, stream_ptr(dev)),
+          "coulomb_hvp")
+    return hx, hy
+
+
+def validate(x, y):
+    """Per-charge domain flags (CD_FLAG_* bits) and the flagged count."""
+    dev = _chk(x, y)
+    n = x.numel()
+    flags = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    ws, nb = workspace(OP_VALIDATE, n, FP64, dev)
+    check(lib().coulomb_validate(x.data_ptr(), y.data_ptr(), n, flags.data_ptr(), cnt.data_ptr(),
+                                 ws.data_ptr(), nb, stream_ptr(dev)), "coulomb_validate")
+    return flags, cnt

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every symbol its header declares;
+argument errors are reported before anything touches a GPU (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2609_24722_amd", "libcoulombdisk.so")
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M):
+            if m.group(1) not in ("if", "while", "defined"):
+                names.append(m.group(1))
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ["coulomb_energy", "coulomb_forces", "coulomb_hvp",
+              "coulomb_workspace_bytes", "coulomb_validate", "coulomb_status_string"]:
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_workspace_sizes_are_host_computable(L):
+    f = L.coulomb_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int]
+    for op in (0, 1, 2, 3):
+        for prec in (0, 1):
+            a = f(op, 1000, 0, 0, prec)
+            b = f(op, 100000, 0, 0, prec)
+            assert 0 < a < b
+    assert f(1, 0, 0, 0, 0) == 0          # n < 1
+    assert f(1, 100, 0, 0, 7) == 0        # bad precision
+
+
+def test_argument_errors_before_any_launch(L):
+    vp = ctypes.c_void_p
+    L.coulomb_forces.restype = ctypes.c_int
+    L.coulomb_forces.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    fake = vp(256)
+    assert L.coulomb_forces(None, fake, 10, 0, fake, fake, None, fake, 1 << 30, None) == -1
+    assert L.coulomb_forces(fake, fake, 10, 0, fake, fake, None, None, 0, None) == -2
+    assert L.coulomb_forces(fake, fake, 10, 0, fake, fake, None, fake, 16, None) == -2
+    assert L.coulomb_forces(fake, fake, 0, 0, fake, fake, None, fake, 1 << 30, None) == -1
+    L.coulomb_status_string.restype = ctypes.c_char_p
+    assert L.coulomb_status_string(-2) == b"workspace missing or too small"

@@ -1,0 +1,135 @@
+"""GPU parity of energy, forces and HVP against the CPU oracle (through the C ABI).
+
+Tolerances: FP64 path energy 1e-13 relative, forces and HVP 1e-11 relative RMS;
+mixed path forces and HVP 1e-5 relative RMS, energy 1e-7 relative (the mixed
+energy has no stated bound; 1e-7 is the FP32 budget of one 1/r term, about
+1.7 ulp of FP32: v_rsq_f32 is within one ulp and the FP32 partials fold into
+FP64 every 64 terms, so the total cannot do worse than its worst term by more
+than the partial-sum rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2609_24722_amd import FP64, MIXED, ops, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {FP64: dict(E=1e-13, F=1e-11, H=1e-11, e=1e-12), MIXED: dict(E=1e-7, F=1e-5, H=1e-5, e=1e-6)}
+
+
+def rel_rms(ax, ay, bx, by):
+    den = np.sqrt(np.sum(bx ** 2 + by ** 2))
+    return np.sqrt(np.sum((ax - bx) ** 2 + (ay - by) ** 2)) / max(den, 1e-300)
+
+
+def cases():
+    out = []
+    for n in (1, 2, 3, 17, 64, 65, 127, 700):
+        out.append((f"uniform{n}", *W.uniform_disk(n, 3000 + n)))
+    out.append(("workload1", *W.workload(1)))
+    out.append(("lattice4097", *W.warped_lattice(4097, 0.1, 77)))
+    out.append(("lattice20000", *W.warped_lattice(20000, 0.02, 78)))
+    return out
+
+
+CASES = cases()
+
+
+def t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_energy_forces_hvp_parity(dev, case, prec):
+    name, x, y = case
+    print(f"[case] {name} n={x.size} prec={prec}", flush=True)
+    n = x.size
+    xt, yt = t(x, dev), t(y, dev)
+    vx, vy = W.unit_vector(n, 4000 + n)
+    tol = TOL[prec]
+    E0, e0 = O.energy(x, y, local=True)
+    fx0, fy0 = O.forces(x, y)
+    hx0, hy0 = O.hvp(x, y, vx, vy)
+    fx, fy, E = ops.forces(xt, yt, prec)
+    E2, e = ops.energy(xt, yt, prec, local=True)
+    E3 = ops.energy(xt, yt, prec)
+    hx, hy = ops.hvp(xt, yt, t(vx, dev), t(vy, dev), prec)
+    torch.cuda.synchronize()
+    if n == 1:
+        assert E.item() == 0.0 and E2.item() == 0.0 and E3.item() == 0.0
+        assert fx.item() == 0.0 and fy.item() == 0.0 and hx.item() == 0.0 and e.item() == 0.0
+        return
+    errE = max(abs(Eg.item() - E0) / E0 for Eg in (E, E2, E3))
+    erre = np.max(np.abs(e.cpu().numpy() - e0) / e0)
+    errF = rel_rms(fx.cpu().numpy(), fy.cpu().numpy(), fx0, fy0)
+    errH = rel_rms(hx.cpu().numpy(), hy.cpu().numpy(), hx0, hy0)
+    print(f"[err] {name} prec={prec} E={errE:.2e} e={erre:.2e} F={errF:.2e} H={errH:.2e}")
+    assert errE <= tol["E"] and erre <= tol["e"] and errF <= tol["F"] and errH <= tol["H"]
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_deterministic_repeat(dev, prec):
+    x, y = W.warped_lattice(9000, 0.05, 5)
+    xt, yt = t(x, dev), t(y, dev)
+    a = ops.forces(xt, yt, prec)
+    b = ops.forces(xt, yt, prec)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_full_size_workload3_sampled(dev, prec):
+    # N = 100000 in the launch configuration the benchmark times: sampled rows
+    # against the oracle, the full energy against the oracle, and identities
+    # that hold at any size (Euler: sum r.F = E; homogeneity: H r = 2F;
+    # Newton's third law).
+    x, y = W.workload(3)
+    n = x.size
+    print(f"[case] workload3 n={n} prec={prec}", flush=True)
+    xt, yt = t(x, dev), t(y, dev)
+    vx, vy = W.unit_vector(n, 1103)
+    tol = TOL[prec]
+    fx, fy, E = ops.forces(xt, yt, prec)
+    E2, e = ops.energy(xt, yt, prec, local=True)
+    hx, hy = ops.hvp(xt, yt, t(vx, dev), t(vy, dev), prec)
+    hrx, hry = ops.hvp(xt, yt, xt, yt, prec)
+    torch.cuda.synchronize()
+    fx, fy, e, hx, hy = (a.cpu().numpy() for a in (fx, fy, e, hx, hy))
+    hrx, hry = hrx.cpu().numpy(), hry.cpu().numpy()
+    rows = np.sort(np.random.default_rng(7).choice(n, 512, replace=False)).astype(np.int32)
+    ofx, ofy, oe = O.rows(x, y, rows)
+    ohx, ohy, _ = O.rows(x, y, rows, vx, vy)
+    _, _, interior = O.rows(x, y, rows)
+    errF = rel_rms(fx[rows], fy[rows], ofx, ofy)
+    inner = np.hypot(x[rows], y[rows]) < 0.9
+    errFi = rel_rms(fx[rows][inner], fy[rows][inner], ofx[inner], ofy[inner])
+    erre = np.max(np.abs(e[rows] - oe) / oe)
+    errH = rel_rms(hx[rows], hy[rows], ohx, ohy)
+    E0 = O.energy(x, y)
+    errE = max(abs(E.item() - E0), abs(E2.item() - E0)) / E0
+    euler = abs(np.sum(x * fx + y * fy) - E0) / E0
+    homog = rel_rms(hrx, hry, 2 * fx, 2 * fy)
+    print(f"[err] workload3 prec={prec} E={errE:.2e} e={erre:.2e} F={errF:.2e} F(|r|<0.9)={errFi:.2e} "
+          f"H={errH:.2e} euler={euler:.2e} Hr=2F:{homog:.2e}")
+    assert errF <= tol["F"] and erre <= tol["e"] and errH <= tol["H"] and errE <= tol["E"]
+    assert euler <= max(10 * tol["F"], 1e-12)
+    assert homog <= 10 * tol["H"]
+    scale = np.sum(np.abs(fx)) + np.sum(np.abs(fy))
+    assert abs(fx.sum()) <= 1e-6 * scale and abs(fy.sum()) <= 1e-6 * scale
+
+
+def test_validate_flags(dev):
+    x, y = W.uniform_disk(300, 9)
+    x[3], y[3] = np.nan, 0.0
+    x[10], y[10] = 1.0 + 1e-9, 0.0
+    x[20], y[20] = x[21], y[21]
+    f, c = ops.validate(t(x, dev), t(y, dev))
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    assert f[3] & 1 and f[10] & 2 and f[20] & 4 and f[21] & 4
+    assert c.item() == int(np.count_nonzero(f))
+    assert np.count_nonzero(f) == 4

@@ -286,3 +286,19 @@ def test_asymptotic_expansion_golden():
     assert abs(Ea - g["E_asym_printed"]) <= 5e-13 * Ea
     dev = abs(g["E_min_printed"] - Ea) / Ea
     assert abs(dev - g["deviation_printed"]) <= 5e-10
+
+
+def test_rows_match_full_sums():
+    x, y = random_config(300, 21)
+    vx, vy = W.unit_vector(x.size, 4)
+    r = np.array([0, 5, 299, 150], dtype=np.int32)
+    fx, fy = O.forces(x, y)
+    hx, hy = O.hvp(x, y, vx, vy)
+    _, e = O.energy(x, y, local=True)
+    a, b, c = O.rows(x, y, r)
+    np.testing.assert_array_equal(a, fx[r])
+    np.testing.assert_array_equal(b, fy[r])
+    np.testing.assert_allclose(c, e[r], rtol=1e-15)
+    a, b, _ = O.rows(x, y, r, vx, vy)
+    np.testing.assert_array_equal(a, hx[r])
+    np.testing.assert_array_equal(b, hy[r])
