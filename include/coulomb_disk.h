@@ -94,6 +94,66 @@ int coulomb_hvp(const double* x, const double* y, const double* vx, const double
 int coulomb_validate(const double* x, const double* y, int64_t n, int32_t* flags_out,
                      int32_t* count_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Subdomains (paper Sec. II.C-E).  A batch of P patches is described by
+ * host offsets patch_ptr[P+1] (patch_ptr[0] = 0, patch p holds the packed
+ * entries patch_ptr[p] .. patch_ptr[p+1]-1) and a device array
+ * active_idx[patch_ptr[P]] of charge indices.  Patches may overlap; each is
+ * relaxed against the same frozen snapshot. */
+
+/* Patch construction (Sec. II.C step 3-4, Sec. II.E sizes): patch p is the
+ * patch_ptr[p+1]-patch_ptr[p] charges nearest to charge centres[p] (device
+ * int32 [P]) by squared Euclidean distance computed in FP64 as
+ * (dx*dx) + (dy*dy) without fused multiply-add, ties to the lower index,
+ * written to active_idx in increasing index order.  ws: at least
+ * coulomb_workspace_bytes(CD_OP_PATCHES, n, P, 0, 0) bytes.  Synchronises
+ * the stream before returning. */
+int build_patches(const double* x, const double* y, int64_t n, int32_t n_patches,
+                  const int32_t* centres, const int32_t* patch_ptr, int32_t* active_idx,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Options of relax_subdomains (host struct). */
+typedef struct {
+  int32_t precision; /* CD_FP64: exact FP64 evaluations throughout (O(n_act N) per
+                        gradient); CD_MIXED: rounds of [exact FP64 far-field expansion
+                        at the current positions (its gradient is the exact one, tested
+                        against gtol); L-BFGS on the model = explicit active and halo
+                        pairs (FP32 while the exact gradient exceeds inner_tol, FP64
+                        after) + the expanded far field as a quadratic] */
+  int32_t max_iter;  /* L-BFGS iterations: CD_FP64 in total, CD_MIXED per round */
+  int32_t lbfgs_m;   /* L-BFGS memory, 1..16 (0 = 8); the workspace is sized for 16 */
+  int32_t max_outer; /* CD_MIXED: rounds, each one exact far-field expansion (0 = 40) */
+  double gtol;       /* tolerance on the inf-norm of the exact FP64 reduced gradient */
+  double inner_tol;  /* CD_MIXED: FP32 pairs while the exact gradient exceeds this
+                        (0 = 3e-2 / h^2) */
+  double halo_width; /* CD_MIXED: halo width in units of h (0 = 4) */
+  double step0;      /* largest displacement of an L-BFGS trial step (0 = 0.1 h) */
+} cd_relax_opts;
+
+/* Relax every patch of the batch (Sec. II.C step 4) against the frozen
+ * snapshot (x, y)[n]: minimise E_sub = sum_{i in A} e_i (Eqs. 6-7, 1/2 on
+ * active-active pairs) over the active positions subject to |r| <= 1 (Eq. 3),
+ * by L-BFGS with wall-held charges moving on the circle.
+ *   x_start, y_start: packed start positions [patch_ptr[P]] (device) or both
+ *     NULL for the snapshot positions; starts outside the disk are projected.
+ *   x_out, y_out (nullable pair): packed relaxed positions.
+ *   dE[P]: E_sub(relaxed) - E_sub(snapshot), exact FP64 pair differences.
+ *   e_sub[P]: exact FP64 E_sub at the relaxed positions.
+ *   gtan_inf[P]: inf-norm of the exact FP64 reduced gradient there.
+ *   iters[2P]: accepted L-BFGS iterations (all stages) and exact FP64
+ *     evaluations per patch.
+ *   status[P]: 0 converged (gtan_inf <= gtol), 1 iteration cap, 2 line search
+ *     failed, 3 non-finite.
+ * Output pointers other than x_out/y_out may be NULL.  ws: at least
+ * coulomb_workspace_bytes(CD_OP_RELAX, n, P, patch_ptr[P], opts->precision).
+ * Reads a few per-round flags back to the host and synchronises the stream
+ * before returning. */
+int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patches,
+                     const int32_t* patch_ptr, const int32_t* active_idx,
+                     const double* x_start, const double* y_start, const cd_relax_opts* opts,
+                     double* x_out, double* y_out, double* dE, double* e_sub,
+                     double* gtan_inf, int32_t* iters, int32_t* status, void* ws,
+                     size_t ws_bytes, void* stream);
+
 /* Measurement hook: when ev_start/ev_stop (hipEvent_t passed as void*) are
  * non-NULL, every later energy/forces/HVP call records ev_start immediately
  * before and ev_stop immediately after its dominant pair kernel, on the

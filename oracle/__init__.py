@@ -235,6 +235,22 @@ def reduce_grad(xa, ya, gx, gy):
     return tx, ty, cons, m
 
 
+def patches(x, y, centres, sizes):
+    """Patch p = the sizes[p] charges nearest to charge centres[p]: squared
+    distance (dx*dx)+(dy*dy) in FP64 (no fused multiply-add), ties to the lower
+    index; each patch listed in increasing index order, patches concatenated."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    idx = np.arange(x.size)
+    out = []
+    for c, k in zip(np.asarray(centres), np.asarray(sizes)):
+        dx = x - x[c]
+        dy = y - y[c]
+        d2 = dx * dx + dy * dy
+        out.append(np.sort(np.lexsort((idx, d2))[:k]))
+    return np.concatenate(out).astype(np.int32)
+
+
 def spacing(n: int) -> float:
     """Mean triangular-lattice spacing for n charges in the unit disk."""
     return float(np.sqrt(2.0 * np.pi / (np.sqrt(3.0) * n)))

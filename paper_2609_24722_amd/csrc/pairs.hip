@@ -498,7 +498,7 @@ __device__ __forceinline__ void one64_block(const double* __restrict__ xb,
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_one64(OneArgs a) {
-  const int I = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int I = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (I >= a.nb) return;
   const int si = I * kBlk + lane;

@@ -1,10 +1,1445 @@
-// Subdomain relaxation (filled in below).
+// Subdomain relaxation (paper Sec. II.C step 4 and Sec. II.E): patch
+// construction, the frozen-exterior field, a batched L-BFGS that relaxes many
+// subdomains at once, exact FP64 energy changes, and the greedy commit of
+// relaxed candidates.
+//
+// Objective of patch p with active set A and frozen set F (Eqs. 6-7 read as
+// E_sub = sum_{i in A} e_i, e_i = 1/2 sum_{j in A} 1/r_ij + sum_{j in F} 1/r_ij):
+// its gradient with respect to an active charge is the full Coulomb gradient
+// from every other charge, frozen ones at their snapshot positions.
+//
+// Two ways to relax a batch:
+//  * CD_FP64 ("plain"): every evaluation is exact -- for each active charge
+//    the sum over all N charges, O(n_act N) per gradient as in Sec. II.E.
+//  * CD_MIXED: the exterior is split into a halo (frozen charges within
+//    halo_width of the patch, kept as explicit pairs) and the far exterior,
+//    whose field at each active charge is summed exactly in FP64 (gradient
+//    and Hessian) at an expansion point and used as a second-order Taylor
+//    model around it.  The model (near pairs explicit, far field quadratic)
+//    is minimised first with FP32 pairs, expanded at the start positions;
+//    then in rounds: re-expand the far field exactly at the current
+//    positions -- at the expansion point the model gradient IS the exact
+//    gradient, which is tested against the tolerance -- and minimise the
+//    FP64-pair model again, keeping the L-BFGS history.  Each round costs one
+//    O(n_act N) FP64 pass; the iterations in between cost O(n_act (n_act +
+//    n_halo)).  The endpoint is a minimiser of the exact E_sub either way.
+//
+// The optimiser (both paths) is L-BFGS over free charges' (x, y) and wall-held
+// charges' polar angle (the paper's boundary parameterisation, Eq. 10, applied
+// to the charges the hard wall of Eq. 3 actually holds), with backtracking on
+// an Armijo test.  All patches advance in lock step: each round is one
+// evaluation kernel over every running patch plus one update kernel with a
+// workgroup per patch.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
 #include "common.hpp"
 
 namespace cd {
+
+size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total_active,
+                             int precision);
+
+constexpr int kMaxMem = 16;  // largest L-BFGS memory; the workspace is sized for it
+
+// ------------------------------------------------------ patch construction --
+__device__ __forceinline__ double dist2_rn(double ax, double ay, double bx, double by) {
+  const double dx = ax - bx, dy = ay - by;
+  return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+}
+
+// One workgroup per patch: the size-th smallest squared distance (as the bit
+// pattern of a non-negative double, which orders like the value) is found by
+// an exact 8-pass radix select; the patch is then every charge below that
+// key plus, among charges equal to it, the lowest indices -- listed in
+// increasing index order.
+__global__ __launch_bounds__(1024) void k_patch_select(const double* __restrict__ x,
+                                                       const double* __restrict__ y, int n,
+                                                       const int32_t* __restrict__ centres,
+                                                       const int32_t* __restrict__ ptr,
+                                                       int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ err) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix, s_mask;
+  __shared__ uint32_t s_need;
+  __shared__ uint32_t lt_cnt[1024], eq_cnt[1024];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int size = ptr[p + 1] - ptr[p];
+  const int ctr = centres[p];
+  if (ctr < 0 || ctr >= n) {  // invalid centre: report, write nothing
+    if (t == 0) atomicOr(err, 1);
+    return;
+  }
+  const double cx = x[ctr], cy = y[ctr];
+  if (t == 0) {
+    s_prefix = 0;
+    s_mask = 0;
+    s_need = (uint32_t)size;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    if (t < 256) hist[t] = 0;
+    __syncthreads();
+    const uint64_t pre = s_prefix, msk = s_mask;
+    for (int j = t; j < n; j += blockDim.x) {
+      const uint64_t key = __double_as_longlong(dist2_rn(x[j], y[j], cx, cy));
+      if ((key & msk) == pre) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+      uint32_t need = s_need, b = 0;
+      while (b < 255 && hist[b] < need) need -= hist[b++];
+      s_need = need;
+      s_prefix = pre | ((uint64_t)b << shift);
+      s_mask = msk | ((uint64_t)255 << shift);
+    }
+    __syncthreads();
+  }
+  const uint64_t T = s_prefix;
+  const uint32_t need_eq = s_need;  // how many charges at exactly T belong to the patch
+  const int chunk = (n + blockDim.x - 1) / blockDim.x;
+  const int j0 = min(n, t * chunk), j1 = min(n, j0 + chunk);
+  uint32_t lt = 0, eq = 0;
+  for (int j = j0; j < j1; ++j) {
+    const uint64_t key = __double_as_longlong(dist2_rn(x[j], y[j], cx, cy));
+    lt += key < T;
+    eq += key == T;
+  }
+  lt_cnt[t] = lt;
+  eq_cnt[t] = eq;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const uint32_t a = t >= off ? lt_cnt[t - off] : 0u, b = t >= off ? eq_cnt[t - off] : 0u;
+    __syncthreads();
+    lt_cnt[t] += a;
+    eq_cnt[t] += b;
+    __syncthreads();
+  }
+  uint32_t lt_before = lt_cnt[t] - lt, eq_before = eq_cnt[t] - eq;
+  int32_t* dst = out + ptr[p];
+  for (int j = j0; j < j1; ++j) {
+    const uint64_t key = __double_as_longlong(dist2_rn(x[j], y[j], cx, cy));
+    if (key < T) {
+      dst[lt_before + min(eq_before, need_eq)] = j;
+      ++lt_before;
+    } else if (key == T) {
+      if (eq_before < need_eq) dst[lt_before + eq_before] = j;
+      ++eq_before;
+    }
+  }
+}
+
+// ------------------------------------------------------------- relax state --
+enum PStatus {
+  kRunning = 0,
+  kConverged = 1,      // current evaluator converged
+  kIterCap = 2,
+  kLineSearchFail = 3,
+  kNonFinite = 4,
+  kDone = 5            // exact reduced gradient met the tolerance (mixed path)
+};
+enum Eval { kEvalExact = 0, kEvalModel32 = 1, kEvalModel64 = 2 };
+
+struct PState {
+  double E, Et;      // objective at z and at the trial zt (current evaluator)
+  double alpha;      // trial step length
+  double gi;         // inf-norm of the reduced gradient at z
+  double R;          // patch radius about its centre
+  double cx, cy;     // patch centre (box centre of the snapshot actives)
+  int it, mem, head, status, init, total_it, exact_evals, evals;
+  int use32;         // mixed path: this round's model uses FP32 pairs
+  int pad;
+};
+
+struct RelaxDev {
+  // sizes
+  int n, P, nbN, m, ntot, nblk, splits, jb;
+  // snapshot and packed active data
+  const double* x;
+  const double* y;
+  const int32_t* ptr;      // [P+1]
+  const int32_t* idx;      // [ntot] charge index of packed active a
+  int32_t* pid;            // [ntot] patch of packed active a
+  int2* blk;               // [nblk] (patch, first packed active) per 64-active block
+  uint64_t* maskA;         // [P][nbN] membership of A_p (original order)
+  uint64_t* maskAH;        // [P][nbN] membership of A_p and its halo
+  double *z0x, *z0y;       // snapshot positions of actives
+  double *zx, *zy;         // current
+  double *tx, *ty;         // trial
+  double *gx, *gy;         // gradient at z (current evaluator)
+  double *hgx, *hgy;       // gradient at the trial
+  double *kxx, *kxy, *kyy;     // preconditioner: the charge's own 2x2 Hessian block at z
+  double *hkxx, *hkxy, *hkyy;  // the same at the trial
+  double *pkxx, *pkxy, *pkyy;  // [splits][ntot] split partials of the blocks
+  double *dx, *dy;         // search direction (coordinates: held -> angle in dx)
+  double *Sx, *Sy, *Yx, *Yy;  // L-BFGS history [m][ntot]
+  double* rho;             // [P][m]
+  int32_t* held;           // [ntot]
+  double* eterm;           // [ntot] per-active energy contribution of the last evaluation
+  double *px, *py, *pe;    // [splits][ntot] split partials of the exact evaluation
+  // mixed-path model
+  double *fgx, *fgy;       // far-field gradient at the snapshot
+  double *fhxx, *fhxy, *fhyy;  // far-field Hessian at the snapshot
+  double *zrx, *zry;       // expansion point of the far-field model
+  int32_t* hptr;           // [P+1] halo CSR
+  int32_t* hidx;           // halo charge indices
+  int hcap;
+  float *a32x, *a32y;      // actives relative to their patch centre (FP32), refreshed per round
+  float *h32x, *h32y;      // halo relative to the patch centre (FP32)
+  double *h64x, *h64y;     // halo positions, packed (FP64)
+  PState* st;              // [P]
+  int32_t* running;        // [1] number of patches still running
+  // options
+  double tol, step0, c1, noise_rel;
+  int max_iter, eval_all;
+  int32_t* ptr_w;          // [P+1] device copy of the patch offsets (in the workspace)
+  double* ptol;            // [P] per-patch stage tolerance (null: tol)
+  int32_t* err;            // [1] argument error found on the device
+};
+
+// ------------------------------------------------------------ setup kernels --
+__global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
+                                const double* __restrict__ ys) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= R.ntot) return;
+  // patch of a: binary search in ptr
+  int lo = 0, hi = R.P;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (R.ptr[mid] <= a) lo = mid;
+    else hi = mid;
+  }
+  R.pid[a] = lo;
+  int i = R.idx[a];
+  if (i < 0 || i >= R.n) {  // invalid charge index: report, stay in bounds
+    atomicOr(R.err, 1);
+    i = 0;
+  }
+  R.z0x[a] = R.x[i];
+  R.z0y[a] = R.y[i];
+  double sx = xs ? xs[a] : R.x[i], sy = ys ? ys[a] : R.y[i];
+  const double r = sqrt(sx * sx + sy * sy);
+  if (r > 1.0) {
+    sx /= r;
+    sy /= r;
+  }
+  R.zx[a] = sx;
+  R.zy[a] = sy;
+  R.tx[a] = sx;
+  R.ty[a] = sy;
+  R.held[a] = 0;
+  const uint64_t bit = 1ull << (i & 63);
+  atomicOr((unsigned long long*)&R.maskA[(size_t)lo * R.nbN + (i >> 6)], (unsigned long long)bit);
+  atomicOr((unsigned long long*)&R.maskAH[(size_t)lo * R.nbN + (i >> 6)], (unsigned long long)bit);
+}
+
+// Patch centre and radius from the snapshot actives; one workgroup per patch.
+__global__ __launch_bounds__(256) void k_patch_geom(RelaxDev R) {
+  __shared__ double red[4][4];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int a = a0 + t; a < a1; a += blockDim.x) {
+    x0 = fmin(x0, R.z0x[a]);
+    x1 = fmax(x1, R.z0x[a]);
+    y0 = fmin(y0, R.z0y[a]);
+    y1 = fmax(y1, R.z0y[a]);
+  }
+  x0 = wave_min(x0);
+  x1 = wave_max(x1);
+  y0 = wave_min(y0);
+  y1 = wave_max(y1);
+  if ((t & 63) == 0) {
+    red[t >> 6][0] = x0;
+    red[t >> 6][1] = x1;
+    red[t >> 6][2] = y0;
+    red[t >> 6][3] = y1;
+  }
+  __syncthreads();
+  const double cx = 0.5 * (fmin(fmin(red[0][0], red[1][0]), fmin(red[2][0], red[3][0])) +
+                           fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1])));
+  const double cy = 0.5 * (fmin(fmin(red[0][2], red[1][2]), fmin(red[2][2], red[3][2])) +
+                           fmax(fmax(red[0][3], red[1][3]), fmax(red[2][3], red[3][3])));
+  double rm = 0.0;
+  for (int a = a0 + t; a < a1; a += blockDim.x) {
+    const double dx = R.z0x[a] - cx, dy = R.z0y[a] - cy;
+    rm = fmax(rm, sqrt(dx * dx + dy * dy));
+  }
+  rm = wave_max(rm);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6][0] = rm;
+  __syncthreads();
+  if (t == 0) {
+    PState s = {};
+    s.cx = cx;
+    s.cy = cy;
+    s.R = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+    s.status = kRunning;
+    s.init = 1;
+    s.alpha = 1.0;
+    R.st[p] = s;
+  }
+}
+
+// Halo of patch p: frozen charges within R_p + w of the patch centre.  Pass 0
+// counts, pass 1 fills (index order, stable) and marks maskAH.
+__global__ __launch_bounds__(1024) void k_halo(RelaxDev R, double w, int fill,
+                                               int32_t* __restrict__ counts) {
+  __shared__ uint32_t cnt[1024];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const PState s = R.st[p];
+  const double lim = (s.R + w) * (s.R + w);
+  const int chunk = (R.n + blockDim.x - 1) / blockDim.x;
+  const int j0 = min(R.n, t * chunk), j1 = min(R.n, j0 + chunk);
+  uint32_t c = 0;
+  for (int j = j0; j < j1; ++j) {
+    const bool act = (R.maskA[(size_t)p * R.nbN + (j >> 6)] >> (j & 63)) & 1ull;
+    const double dx = R.x[j] - s.cx, dy = R.y[j] - s.cy;
+    c += (!act && dx * dx + dy * dy <= lim);
+  }
+  cnt[t] = c;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const uint32_t v = t >= off ? cnt[t - off] : 0u;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  if (!fill) {
+    if (t == 0) counts[p] = (int32_t)cnt[blockDim.x - 1];
+    return;
+  }
+  uint32_t pos = R.hptr[p] + cnt[t] - c;
+  for (int j = j0; j < j1; ++j) {
+    const bool act = (R.maskA[(size_t)p * R.nbN + (j >> 6)] >> (j & 63)) & 1ull;
+    const double dx = R.x[j] - s.cx, dy = R.y[j] - s.cy;
+    if (!act && dx * dx + dy * dy <= lim) {
+      R.hidx[pos++] = j;
+      atomicOr((unsigned long long*)&R.maskAH[(size_t)p * R.nbN + (j >> 6)],
+               (unsigned long long)(1ull << (j & 63)));
+    }
+  }
+}
+
+// ------------------------------------------------------ exact FP64 evaluation --
+// Wave = 64 packed actives of one patch (grid.x over the block table), grid.y
+// = split of the N snapshot charges.  Frozen charges come from the snapshot,
+// skipped when the patch mask marks them; active ones from the trial
+// positions of the same patch.  Charges are wave-uniform and read through the
+// scalar cache.
+//   kGrad : energy contribution and gradient at the trial positions
+//   kFar  : far-field gradient and Hessian at the trial positions, which
+//           become the model's expansion point (mask = A + halo)
+//   kDelta: E_sub(trial) - E_sub(snapshot), pair differences without
+//           cancellation: 1/r' - 1/r = (d - d').(d + d') / (r r' (r + r'))
+enum ExactMode { kGrad = 0, kFar = 1, kDelta = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
+  // the wave index is uniform within a wave; saying so lets the compiler keep
+  // patch data in SGPRs and read the j charges through the scalar cache
+  const int wb = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (wb >= R.nblk) return;
+  const int2 bk = R.blk[wb];
+  const int p = bk.x;
+  if (MODE == kGrad && !R.eval_all && R.st[p].status != kRunning) return;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  const int a = bk.y + lane;
+  const bool ok = a < a1;
+  const int ac = ok ? a : a1 - 1;
+  const double xi = R.tx[ac];
+  const double yi = R.ty[ac];
+  const double xo = R.z0x[ac], yo = R.z0y[ac];  // snapshot position (kDelta)
+  const uint64_t* mask = (MODE == kFar ? R.maskAH : R.maskA) + (size_t)p * R.nbN;
+  double G0 = 0.0, G1 = 0.0, G2 = 0.0, G3 = 0.0, G4 = 0.0, Ee = 0.0, Ec = 0.0;
+  const int J0 = blockIdx.y * R.jb, J1 = min(R.nbN, J0 + R.jb);
+  for (int J = J0; J < J1; ++J) {
+    const uint64_t m = mask[J];  // wave-uniform: charges of the patch (and halo) are skipped
+    const int jn = min(64, R.n - J * 64);
+    const double* xb = R.x + (size_t)J * 64;
+    const double* yb = R.y + (size_t)J * 64;
+    double eb = 0.0;
+#pragma unroll 8
+    for (int jj = 0; jj < jn; ++jj) {
+      const bool skip = (m >> jj) & 1ull;
+      const double xj = xb[jj], yj = yb[jj];
+      const double dx = xi - xj, dy = yi - yj;
+      const double r2 = __builtin_fma(dx, dx, dy * dy);
+      if (MODE == kDelta) {
+        const double ox = xo - xj, oy = yo - yj;
+        const double ro2 = __builtin_fma(ox, ox, oy * oy);
+        const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
+        const double rn = r2 * ri, ro = ro2 * roi;
+        const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
+        const double v = num * ri * roi / (rn + ro);
+        eb += skip ? 0.0 : v;
+      } else {
+        double inv = rsqrt64(r2);
+        inv = skip ? 0.0 : inv;
+        const double i3 = inv * inv * inv;
+        G0 = __builtin_fma(-dx, i3, G0);
+        G1 = __builtin_fma(-dy, i3, G1);
+        if (MODE == kGrad) eb += inv;
+        const double i5 = i3 * inv * inv;
+        const double t3 = 3.0 * i5;
+        G2 += __builtin_fma(t3 * dx, dx, -i3);
+        G3 += t3 * dx * dy;
+        G4 += __builtin_fma(t3 * dy, dy, -i3);
+      }
+    }
+    const double tt = Ee + eb;  // Neumaier across 64-charge blocks
+    Ec += fabs(Ee) >= fabs(eb) ? (Ee - tt) + eb : (eb - tt) + Ee;
+    Ee = tt;
+  }
+  if (MODE != kFar && blockIdx.y == 0) {
+    // active-active pairs at the trial positions (half weight in the energy)
+#pragma unroll 4
+    for (int b = a0; b < a1; ++b) {
+      const double xj = R.tx[b], yj = R.ty[b];
+      const double dx = xi - xj, dy = yi - yj;
+      const double r2 = __builtin_fma(dx, dx, dy * dy);
+      if (MODE == kDelta) {
+        const double ox = xo - R.z0x[b], oy = yo - R.z0y[b];
+        const double ro2 = __builtin_fma(ox, ox, oy * oy);
+        double v = 0.0;
+        if (b != ac) {
+          const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
+          const double rn = r2 * ri, ro = ro2 * roi;
+          const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
+          v = 0.5 * (num * ri * roi / (rn + ro));
+        }
+        const double tt = Ee + v;
+        Ec += fabs(Ee) >= fabs(v) ? (Ee - tt) + v : (v - tt) + Ee;
+        Ee = tt;
+      } else {
+        double inv = rsqrt64(r2);
+        inv = (b == ac) ? 0.0 : inv;
+        const double i3 = inv * inv * inv;
+        const double h = 0.5 * inv;
+        const double tt = Ee + h;
+        Ec += fabs(Ee) >= fabs(h) ? (Ee - tt) + h : (h - tt) + Ee;
+        Ee = tt;
+        G0 = __builtin_fma(-dx, i3, G0);
+        G1 = __builtin_fma(-dy, i3, G1);
+        const double t3 = 3.0 * i3 * inv * inv;
+        G2 += __builtin_fma(t3 * dx, dx, -i3);
+        G3 += t3 * dx * dy;
+        G4 += __builtin_fma(t3 * dy, dy, -i3);
+      }
+    }
+  }
+  if (!ok) return;
+  const size_t q = (size_t)blockIdx.y * R.ntot + a;
+  if (MODE == kFar) {
+    R.zrx[a] = xi;  // kFar runs with a single split
+    R.zry[a] = yi;
+    R.fgx[a] = G0;
+    R.fgy[a] = G1;
+    R.fhxx[a] = G2;
+    R.fhxy[a] = G3;
+    R.fhyy[a] = G4;
+  } else {
+    R.px[q] = G0;
+    R.py[q] = G1;
+    R.pe[q] = Ee + Ec;
+    if (MODE == kGrad) {
+      R.pkxx[q] = G2;
+      R.pkxy[q] = G3;
+      R.pkyy[q] = G4;
+    }
+  }
+}
+
+// Sum the split partials (fixed order) into the trial gradient / energy terms.
+__global__ void k_exact_sum(RelaxDev R, int grad) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= R.ntot) return;
+  double g0 = 0.0, g1 = 0.0, e = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0;
+  for (int s = 0; s < R.splits; ++s) {
+    const size_t q = (size_t)s * R.ntot + a;
+    g0 += R.px[q];
+    g1 += R.py[q];
+    e += R.pe[q];
+    if (grad) {
+      k0 += R.pkxx[q];
+      k1 += R.pkxy[q];
+      k2 += R.pkyy[q];
+    }
+  }
+  if (grad) {
+    R.hgx[a] = g0;
+    R.hgy[a] = g1;
+    R.hkxx[a] = k0;
+    R.hkxy[a] = k1;
+    R.hkyy[a] = k2;
+  }
+  R.eterm[a] = e;
+}
+
+// ------------------------------------------------------------ model evaluation --
+// Active i against its patch's other actives (trial positions) and its halo
+// (snapshot), plus the far field as a Taylor model about the expansion point:
+//   E_i = 1/2 sum_A 1/r + sum_halo 1/r + f.d + 1/2 d.H d,  d = z_i - zr_i
+// Per patch either FP32 pairs (coordinates relative to the patch centre,
+// partials of at most 64 terms folded into FP64) or FP64 pairs.
+template <bool SELF>
+__device__ __forceinline__ void pairs32(const float* __restrict__ xs, const float* __restrict__ ys,
+                                        int b0, int b1, int self, float xf, float yf, double& G0,
+                                        double& G1, double& E, double* K, double w) {
+  for (int c0 = b0; c0 < b1; c0 += 64) {
+    const int c1 = min(b1, c0 + 64);
+    float g0 = 0.f, g1 = 0.f, e = 0.f, k0 = 0.f, k1 = 0.f, k2 = 0.f;
+#pragma unroll 8
+    for (int b = c0; b < c1; ++b) {
+      const float dx = xf - xs[b], dy = yf - ys[b];
+      const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+      float inv = __builtin_amdgcn_rsqf(r2);
+      if (SELF) inv = (b == self) ? 0.f : inv;
+      const float i3 = inv * inv * inv;
+      e += inv;
+      g0 = __builtin_fmaf(-dx, i3, g0);
+      g1 = __builtin_fmaf(-dy, i3, g1);
+      const float t3 = 3.0f * i3 * inv * inv;
+      k0 += __builtin_fmaf(t3 * dx, dx, -i3);
+      k1 += t3 * dx * dy;
+      k2 += __builtin_fmaf(t3 * dy, dy, -i3);
+    }
+    G0 += g0;
+    G1 += g1;
+    E += w * (double)e;
+    K[0] += k0;
+    K[1] += k1;
+    K[2] += k2;
+  }
+}
+
+template <bool SELF>
+__device__ __forceinline__ void pairs64(const double* __restrict__ xs,
+                                        const double* __restrict__ ys, int b0, int b1, int self,
+                                        double xi, double yi, double& G0, double& G1, double& E,
+                                        double& Ec, double* K, double w) {
+  for (int c0 = b0; c0 < b1; c0 += 64) {
+    const int c1 = min(b1, c0 + 64);
+    double e = 0.0;
+#pragma unroll 4
+    for (int b = c0; b < c1; ++b) {
+      const double dx = xi - xs[b], dy = yi - ys[b];
+      const double r2 = __builtin_fma(dx, dx, dy * dy);
+      double inv = rsqrt64(r2);
+      if (SELF) inv = (b == self) ? 0.0 : inv;
+      const double i3 = inv * inv * inv;
+      e += inv;
+      G0 = __builtin_fma(-dx, i3, G0);
+      G1 = __builtin_fma(-dy, i3, G1);
+      const double t3 = 3.0 * i3 * inv * inv;
+      K[0] += __builtin_fma(t3 * dx, dx, -i3);
+      K[1] += t3 * dx * dy;
+      K[2] += __builtin_fma(t3 * dy, dy, -i3);
+    }
+    const double v = w * e;
+    const double tt = E + v;
+    Ec += fabs(E) >= fabs(v) ? (E - tt) + v : (v - tt) + E;
+    E = tt;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_model(RelaxDev R) {
+  // the wave index is uniform within a wave; saying so lets the compiler keep
+  // patch data in SGPRs and read the j charges through the scalar cache
+  const int wb = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (wb >= R.nblk) return;
+  const int2 bk = R.blk[wb];
+  const int p = bk.x;
+  const PState& st = R.st[p];
+  if (!R.eval_all && st.status != kRunning) return;
+  const bool use32 = st.use32;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
+  const int a = bk.y + lane;
+  const bool ok = a < a1;
+  const int ac = ok ? a : a1 - 1;
+  const double xi = R.tx[ac], yi = R.ty[ac];
+  double G0 = 0.0, G1 = 0.0, E = 0.0, K[3] = {0.0, 0.0, 0.0};
+  if (use32) {
+    const float xf = R.a32x[ac], yf = R.a32y[ac];
+    pairs32<true>(R.a32x, R.a32y, a0, a1, ac, xf, yf, G0, G1, E, K, 0.5);
+    pairs32<false>(R.h32x, R.h32y, h0, h1, -1, xf, yf, G0, G1, E, K, 1.0);
+  } else {
+    double Ec = 0.0;
+    pairs64<true>(R.tx, R.ty, a0, a1, ac, xi, yi, G0, G1, E, Ec, K, 0.5);
+    pairs64<false>(R.h64x, R.h64y, h0, h1, -1, xi, yi, G0, G1, E, Ec, K, 1.0);
+    E += Ec;
+  }
+  if (!ok) return;
+  const double ddx = xi - R.zrx[a], ddy = yi - R.zry[a];
+  const double hx = R.fhxx[a] * ddx + R.fhxy[a] * ddy, hy = R.fhxy[a] * ddx + R.fhyy[a] * ddy;
+  E += R.fgx[a] * ddx + R.fgy[a] * ddy + 0.5 * (ddx * hx + ddy * hy);
+  R.hgx[a] = G0 + R.fgx[a] + hx;
+  R.hgy[a] = G1 + R.fgy[a] + hy;
+  R.hkxx[a] = K[0] + R.fhxx[a];
+  R.hkxy[a] = K[1] + R.fhxy[a];
+  R.hkyy[a] = K[2] + R.fhyy[a];
+  R.eterm[a] = E;
+}
+
+// FP32 coordinates of trial actives relative to the patch centre; with
+// halo_too also the halo, packed (FP64 and FP32 relative).
+__global__ void k_model_prep(RelaxDev R, int halo_too) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < R.ntot) {
+    const PState& s = R.st[R.pid[a]];
+    R.a32x[a] = (float)(R.tx[a] - s.cx);
+    R.a32y[a] = (float)(R.ty[a] - s.cy);
+  }
+  if (halo_too && a < R.hptr[R.P]) {
+    int lo = 0, hi = R.P;  // patch of halo entry a
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (R.hptr[mid] <= a) lo = mid;
+      else hi = mid;
+    }
+    const PState& s = R.st[lo];
+    const int j = R.hidx[a];
+    R.h64x[a] = R.x[j];
+    R.h64y[a] = R.y[j];
+    R.h32x[a] = (float)(R.x[j] - s.cx);
+    R.h32y[a] = (float)(R.y[j] - s.cy);
+  }
+}
+
+// ------------------------------------------------------------ update kernel --
+// One workgroup per patch.  Accept/reject the trial (Armijo, or a reduced
+// gradient decrease when the energy change is below the evaluation's noise),
+// update the L-BFGS history and the wall-held set, test convergence, and
+// form the next trial point.
+constexpr int kUpd = 256;
+
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+__device__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// reduced gradient component magnitude at position (px, py) with gradient g:
+// a charge on the wall whose gradient points inward is held and keeps only
+// the tangential part
+__device__ __forceinline__ bool held_rule(double px, double py, double g0, double g1) {
+  const double r = sqrt(px * px + py * py);
+  return r >= 1.0 - 1e-14 && (g0 * px + g1 * py) < 0.0;
+}
+__device__ __forceinline__ double reduced_inf(double px, double py, double g0, double g1) {
+  if (held_rule(px, py, g0, g1)) {
+    const double r = sqrt(px * px + py * py);
+    const double ux = px / r, uy = py / r, gr = g0 * ux + g1 * uy;
+    return fmax(fabs(g0 - gr * ux), fabs(g1 - gr * uy));
+  }
+  return fmax(fabs(g0), fabs(g1));
+}
+// gradient in optimisation coordinates: (gx, gy) for a free charge, (dE/dtheta, 0) for a held one
+__device__ __forceinline__ void coord_grad(bool h, double px, double py, double g0, double g1,
+                                           double& c0, double& c1) {
+  if (h) {
+    c0 = -g0 * py + g1 * px;
+    c1 = 0.0;
+  } else {
+    c0 = g0;
+    c1 = g1;
+  }
+}
+
+__device__ void take_step(bool h, double px, double py, double d0, double d1, double al,
+                          double& nx, double& ny) {
+  if (h) {
+    double sn, cs;
+    sincos(al * d0, &sn, &cs);
+    nx = px * cs - py * sn;
+    ny = px * sn + py * cs;
+  } else {
+    nx = px + al * d0;
+    ny = py + al * d1;
+  }
+  const double r = sqrt(nx * nx + ny * ny);
+  if (r > 1.0) {
+    nx /= r;
+    ny /= r;
+  }
+}
+
+// Preconditioner H0 = inverse of the charge's own Hessian block (its 2x2
+// block for a free charge; d2E/dtheta2 = t.K.t - g.r_hat for a held one),
+// with |eigenvalues| floored at 1e-3 of the largest when the block is not
+// positive definite.  r = H0 q.
+__device__ void apply_prec(bool held, double px, double py, double g0, double g1, double a,
+                           double b, double c, double q0, double q1, double& r0, double& r1) {
+  if (held) {
+    const double rr = px * px + py * py;
+    const double tt = (a * py * py - 2.0 * b * px * py + c * px * px) / rr;
+    const double k = tt - (g0 * px + g1 * py) / sqrt(rr);
+    const double f = fmax(fabs(k), 1e-3 * fmax(fabs(a), fabs(c)));
+    r0 = f > 0.0 ? q0 / f : q0;
+    r1 = 0.0;
+    return;
+  }
+  const double tr = a + c, det = a * c - b * b;
+  if (tr > 0.0 && det > 1e-6 * tr * tr) {
+    r0 = (c * q0 - b * q1) / det;
+    r1 = (a * q1 - b * q0) / det;
+    return;
+  }
+  const double m = 0.5 * tr, dd = sqrt(0.25 * (a - c) * (a - c) + b * b);
+  double l1 = m + dd, l2 = m - dd;
+  double vx, vy;
+  if (fabs(b) > 0.0) {
+    vx = b;
+    vy = l1 - a;
+  } else if (a >= c) {
+    vx = 1.0;
+    vy = 0.0;
+  } else {
+    vx = 0.0;
+    vy = 1.0;
+  }
+  const double nv = sqrt(vx * vx + vy * vy);
+  const double lmax = fmax(fabs(l1), fabs(l2));
+  if (!(nv > 0.0) || !(lmax > 0.0)) {
+    r0 = q0;
+    r1 = q1;
+    return;
+  }
+  vx /= nv;
+  vy /= nv;
+  l1 = fmax(fabs(l1), 1e-3 * lmax);
+  l2 = fmax(fabs(l2), 1e-3 * lmax);
+  const double p1 = vx * q0 + vy * q1, p2 = -vy * q0 + vx * q1;
+  r0 = vx * (p1 / l1) - vy * (p2 / l2);
+  r1 = vy * (p1 / l1) + vx * (p2 / l2);
+}
+
+__global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
+  __shared__ double red[4];
+  __shared__ double s_alf[kMaxMem];
+  __shared__ int s_flag;
+  const int p = blockIdx.x, t = threadIdx.x;
+  PState s = R.st[p];
+  if (s.status != kRunning) return;
+  s.evals++;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  const int m = R.m;
+  double* rho = R.rho + (size_t)p * m;
+
+  // energy of the trial (fixed-order block sum of per-active terms)
+  double e = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd) e += R.eterm[a];
+  const double Et = block_sum(e, red);
+  bool accept;
+  bool nonfinite = !isfinite(Et);
+  double shrink = 0.5;  // backtracking factor when the trial is rejected
+  if (s.init) {
+    accept = true;
+  } else {
+    // directional derivatives along the step in optimisation coordinates:
+    // pred = grad(z).s, dpt = grad(zt).s; a held charge's step is the angle
+    // alpha*d (its Cartesian displacement has a second-order radial part that
+    // the large wall reaction would weigh), a free charge's is zt - z
+    double pr = 0.0, pt = 0.0;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      if (R.held[a]) {
+        const double st = s.alpha * R.dx[a];
+        pr += (-R.gx[a] * R.zy[a] + R.gy[a] * R.zx[a]) * st;
+        pt += (-R.hgx[a] * R.ty[a] + R.hgy[a] * R.tx[a]) * st;
+      } else {
+        const double ddx = R.tx[a] - R.zx[a], ddy = R.ty[a] - R.zy[a];
+        pr += R.gx[a] * ddx + R.gy[a] * ddy;
+        pt += R.hgx[a] * ddx + R.hgy[a] * ddy;
+      }
+    }
+    const double pred = block_sum(pr, red);
+    const double dpt = block_sum(pt, red);
+    const double dE = Et - s.E;
+    const double noise = (s.use32 ? 1e-9 : R.noise_rel) * fabs(s.E);
+    if (fabs(dE) > noise) {
+      accept = dE <= R.c1 * pred;  // Armijo
+    } else {
+      // energy change below the evaluation's rounding: derivative-only test
+      // (curvature condition) and a secant step back on an overshoot
+      accept = pred < 0.0 && dpt <= 0.9 * fabs(pred);
+      if (pred < 0.0 && dpt > pred) shrink = fmin(0.5, fmax(0.1, pred / (pred - dpt)));
+    }
+  }
+  if (nonfinite) {
+    if (t == 0) {
+      s.status = kNonFinite;
+      R.st[p] = s;
+      atomicSub(R.running, 1);
+    }
+    return;
+  }
+
+  if (accept) {
+    // secant pair in the coordinates of the step just taken (held flags at z)
+    if (!s.init) {
+      double syp = 0.0, ssp = 0.0, yyp = 0.0;
+      const int k = s.head;
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        const bool h = R.held[a];
+        double s0, s1, c0, c1, n0, n1;
+        if (h) {
+          s0 = s.alpha * R.dx[a];
+          s1 = 0.0;
+        } else {
+          s0 = R.tx[a] - R.zx[a];
+          s1 = R.ty[a] - R.zy[a];
+        }
+        coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+        coord_grad(h, R.tx[a], R.ty[a], R.hgx[a], R.hgy[a], n0, n1);
+        const double y0 = n0 - c0, y1 = n1 - c1;
+        const size_t q = (size_t)k * R.ntot + a;
+        R.Sx[q] = s0;
+        R.Sy[q] = s1;
+        R.Yx[q] = y0;
+        R.Yy[q] = y1;
+        syp += s0 * y0 + s1 * y1;
+        ssp += s0 * s0 + s1 * s1;
+        yyp += y0 * y0 + y1 * y1;
+      }
+      const double sy = block_sum(syp, red), ss = block_sum(ssp, red), yy = block_sum(yyp, red);
+      if (sy > 1e-12 * sqrt(ss * yy)) {
+        if (t == 0) rho[k] = 1.0 / sy;
+        s.head = (s.head + 1) % m;
+        if (s.mem < m) s.mem++;
+      }
+    }
+    // move to the trial, update the held set
+    if (t == 0) s_flag = 0;
+    __syncthreads();
+    double gm = 0.0;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      const double px = R.tx[a], py = R.ty[a], g0 = R.hgx[a], g1 = R.hgy[a];
+      R.zx[a] = px;
+      R.zy[a] = py;
+      R.gx[a] = g0;
+      R.gy[a] = g1;
+      R.kxx[a] = R.hkxx[a];
+      R.kxy[a] = R.hkxy[a];
+      R.kyy[a] = R.hkyy[a];
+      const int h = held_rule(px, py, g0, g1);
+      if (h != R.held[a]) {
+        R.held[a] = h;
+        if (!s.init) {
+          for (int k = 0; k < m; ++k) {
+            const size_t q = (size_t)k * R.ntot + a;
+            R.Sx[q] = R.Sy[q] = R.Yx[q] = R.Yy[q] = 0.0;
+          }
+        }
+        s_flag = 1;
+      }
+      gm = fmax(gm, reduced_inf(px, py, g0, g1));
+    }
+    const double gi = block_max(gm, red);
+    __syncthreads();
+    if (s_flag && s.mem > 0) {
+      for (int k = 0; k < s.mem; ++k) {
+        const int kk = (s.head - 1 - k + m) % m;
+        double sy = 0.0;
+        for (int a = a0 + t; a < a1; a += kUpd) {
+          const size_t q = (size_t)kk * R.ntot + a;
+          sy += R.Sx[q] * R.Yx[q] + R.Sy[q] * R.Yy[q];
+        }
+        sy = block_sum(sy, red);
+        if (t == 0) rho[kk] = sy > 0.0 ? 1.0 / sy : 0.0;
+      }
+    }
+    s.E = Et;
+    s.gi = gi;
+    if (!s.init) {
+      s.it++;
+      s.total_it++;
+    }
+    s.init = 0;
+    const double tol = R.ptol ? R.ptol[p] : R.tol;
+    if (gi <= tol || s.it >= R.max_iter) {
+      if (t == 0) {
+        s.status = gi <= tol ? kConverged : kIterCap;
+        R.st[p] = s;
+        atomicSub(R.running, 1);
+      }
+      return;
+    }
+  } else {
+    s.alpha *= shrink;
+    if (s.alpha >= 1e-10) {
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        double nx, ny;
+        take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], s.alpha, nx, ny);
+        R.tx[a] = nx;
+        R.ty[a] = ny;
+      }
+      if (t == 0) R.st[p] = s;
+      return;
+    }
+    if (s.mem == 0) {
+      if (t == 0) {
+        s.status = kLineSearchFail;
+        R.st[p] = s;
+        atomicSub(R.running, 1);
+      }
+      return;
+    }
+    s.mem = 0;  // restart from steepest descent
+    s.head = 0;
+  }
+
+  // new direction: two-loop recursion on the coordinate gradient
+  __syncthreads();
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    double c0, c1;
+    coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+    R.dx[a] = c0;
+    R.dy[a] = c1;
+  }
+  __syncthreads();
+  for (int k = 0; k < s.mem; ++k) {
+    const int kk = (s.head - 1 - k + m) % m;
+    double v = 0.0;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      const size_t q = (size_t)kk * R.ntot + a;
+      v += R.Sx[q] * R.dx[a] + R.Sy[q] * R.dy[a];
+    }
+    const double al = rho[kk] * block_sum(v, red);
+    if (t == 0) s_alf[kk] = al;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      const size_t q = (size_t)kk * R.ntot + a;
+      R.dx[a] -= al * R.Yx[q];
+      R.dy[a] -= al * R.Yy[q];
+    }
+    __syncthreads();
+  }
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    double r0, r1;
+    apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
+               R.dx[a], R.dy[a], r0, r1);
+    R.dx[a] = r0;
+    R.dy[a] = r1;
+  }
+  __syncthreads();
+  for (int k = s.mem - 1; k >= 0; --k) {
+    const int kk = (s.head - 1 - k + m) % m;
+    double v = 0.0;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      const size_t q = (size_t)kk * R.ntot + a;
+      v += R.Yx[q] * R.dx[a] + R.Yy[q] * R.dy[a];
+    }
+    const double be = rho[kk] * block_sum(v, red);
+    const double coef = s_alf[kk] - be;
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      const size_t q = (size_t)kk * R.ntot + a;
+      R.dx[a] += coef * R.Sx[q];
+      R.dy[a] += coef * R.Sy[q];
+    }
+    __syncthreads();
+  }
+  // d = -H g; fall back to scaled steepest descent if not a descent direction
+  double dg = 0.0, dm = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    double c0, c1;
+    const bool h = R.held[a];
+    coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+    R.dx[a] = -R.dx[a];
+    R.dy[a] = -R.dy[a];
+    dg += R.dx[a] * c0 + R.dy[a] * c1;
+  }
+  dg = block_sum(dg, red);
+  const bool steep = !(dg < 0.0);
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    if (steep) {
+      double c0, c1, r0, r1;
+      const bool h = R.held[a];
+      coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      apply_prec(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a], c0, c1, r0,
+                 r1);
+      R.dx[a] = -r0;
+      R.dy[a] = -r1;
+    }
+    const double l = R.held[a] ? fabs(R.dx[a]) : sqrt(R.dx[a] * R.dx[a] + R.dy[a] * R.dy[a]);
+    dm = fmax(dm, l);
+  }
+  dm = block_max(dm, red);
+  const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
+  s.alpha = 1.0;
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    R.dx[a] *= sc;
+    R.dy[a] *= sc;
+    double nx, ny;
+    take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], 1.0, nx, ny);
+    R.tx[a] = nx;
+    R.ty[a] = ny;
+  }
+  if (t == 0) R.st[p] = s;
+}
+
+// Restart every patch not yet done on a new evaluator: the next evaluation
+// is at z itself (no secant pair from it).  keep_mem keeps the L-BFGS
+// history (the near-field curvature it holds is unchanged by a re-expansion
+// of the far field).
+__global__ void k_restart(RelaxDev R, int keep_mem) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= R.P) return;
+  PState s = R.st[p];
+  if (s.status == kConverged || s.status == kIterCap || s.status == kLineSearchFail)
+    s.status = kRunning;
+  s.init = 1;
+  s.it = 0;
+  if (!keep_mem) {
+    s.mem = 0;
+    s.head = 0;
+  }
+  s.alpha = 1.0;
+  R.st[p] = s;
+}
+
+__global__ void k_copy_z_to_t(RelaxDev R) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= R.ntot) return;
+  R.tx[a] = R.zx[a];
+  R.ty[a] = R.zy[a];
+}
+
+__global__ void k_count_running(RelaxDev R) {
+  __shared__ int c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < R.P; p += blockDim.x)
+    if (R.st[p].status == kRunning) atomicAdd(&c, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *R.running = c;
+}
+
+// After a re-expansion at z and a model evaluation there, (hgx, hgy) is the
+// exact gradient at z: a patch whose exact reduced gradient meets the
+// tolerance is done.  Sets the stage tolerance of the others to a fraction
+// of their current exact gradient.
+__global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double frac,
+                                                double tol32, double* __restrict__ ptol) {
+  __shared__ double red[4];
+  const int p = blockIdx.x, t = threadIdx.x;
+  PState s = R.st[p];
+  if (s.status == kNonFinite || s.status == kDone) return;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double gm = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd)
+    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a]));
+  const double gi = block_max(gm, red);
+  if (t == 0) {
+    s.exact_evals++;
+    s.gi = gi;
+    if (gi <= tol) s.status = kDone;
+    ptol[p] = fmax(0.1 * tol, frac * gi);
+    s.use32 = gi > tol32;
+    R.st[p] = s;
+  }
+}
+
+// Final per-patch outputs after an exact evaluation at z (gradient in hg,
+// energy terms in eterm): positions, E_sub, exact reduced gradient, counters
+// and status (0 converged, 1 iteration cap, 2 line search failed, 3 non-finite).
+__global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exact_evals_all,
+                                                 double* __restrict__ xo, double* __restrict__ yo,
+                                                 double* __restrict__ esub,
+                                                 double* __restrict__ gtan,
+                                                 int32_t* __restrict__ iters,
+                                                 int32_t* __restrict__ status) {
+  __shared__ double red[4];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const PState s = R.st[p];
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double e = 0.0, gm = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    e += R.eterm[a];
+    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a]));
+    if (xo) {
+      xo[a] = R.zx[a];
+      yo[a] = R.zy[a];
+    }
+  }
+  const double E = block_sum(e, red);
+  const double gi = block_max(gm, red);
+  if (t == 0) {
+    if (esub) esub[p] = E;
+    if (gtan) gtan[p] = gi;
+    if (iters) {
+      iters[2 * p] = s.total_it;
+      iters[2 * p + 1] = exact_evals_all ? s.evals + 1 : s.exact_evals + 1;
+    }
+    if (status)
+      status[p] = !(gi <= tol) ? (s.status == kLineSearchFail ? 2 : s.status == kNonFinite ? 3 : 1)
+                               : (isfinite(E) ? 0 : 3);
+  }
+}
+
+__global__ __launch_bounds__(kUpd) void k_finish_delta(RelaxDev R, double* __restrict__ dE) {
+  __shared__ double red[4];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double e = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd) e += R.eterm[a];
+  const double d = block_sum(e, red);
+  if (t == 0 && dE) dE[p] = d;
+}
+
+// ------------------------------------------------------------------ planning --
+struct RPlan {
+  int n, P, nbN, m, ntot, nblk, splits, jb, hcap;
+  size_t total;
+  RelaxDev D;
+  int32_t* hcount;  // [P]
+  int32_t* blk_host_dummy;
+};
+
+static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char* base, RPlan& R) {
+  if (n64 < 2 || n64 > (1 << 26) || P < 1 || ntot64 < 1 || ntot64 > n64 * (int64_t)P) return false;
+  if (precision != CD_FP64 && precision != CD_MIXED) return false;
+  if (m < 1 || m > kMaxMem) return false;
+  R.n = (int)n64;
+  R.P = P;
+  R.ntot = (int)ntot64;
+  R.nbN = (R.n + 63) / 64;
+  R.m = m;
+  R.nblk = R.ntot / 64 + P;  // upper bound of the block table length
+  int sp = (16384 + R.nblk - 1) / R.nblk;
+  sp = sp < 1 ? 1 : (sp > R.nbN ? R.nbN : sp);
+  R.jb = (R.nbN + sp - 1) / sp;
+  R.splits = (R.nbN + R.jb - 1) / R.jb;
+  R.hcap = precision == CD_MIXED ? 6 * R.ntot + 4096 * P : 0;
+  Carve cv;
+  cv.base = base;
+  RelaxDev& D = R.D;
+  const size_t nt = R.ntot;
+  D.pid = cv.take<int32_t>(nt);
+  D.blk = cv.take<int2>(R.nblk);
+  D.maskA = cv.take<uint64_t>((size_t)P * R.nbN);
+  D.maskAH = cv.take<uint64_t>((size_t)P * R.nbN);
+  D.z0x = cv.take<double>(nt);
+  D.z0y = cv.take<double>(nt);
+  D.zx = cv.take<double>(nt);
+  D.zy = cv.take<double>(nt);
+  D.tx = cv.take<double>(nt);
+  D.ty = cv.take<double>(nt);
+  D.gx = cv.take<double>(nt);
+  D.gy = cv.take<double>(nt);
+  D.hgx = cv.take<double>(nt);
+  D.hgy = cv.take<double>(nt);
+  D.kxx = cv.take<double>(nt);
+  D.kxy = cv.take<double>(nt);
+  D.kyy = cv.take<double>(nt);
+  D.hkxx = cv.take<double>(nt);
+  D.hkxy = cv.take<double>(nt);
+  D.hkyy = cv.take<double>(nt);
+  D.pkxx = cv.take<double>(nt * R.splits);
+  D.pkxy = cv.take<double>(nt * R.splits);
+  D.pkyy = cv.take<double>(nt * R.splits);
+  D.dx = cv.take<double>(nt);
+  D.dy = cv.take<double>(nt);
+  D.Sx = cv.take<double>(nt * m);
+  D.Sy = cv.take<double>(nt * m);
+  D.Yx = cv.take<double>(nt * m);
+  D.Yy = cv.take<double>(nt * m);
+  D.rho = cv.take<double>((size_t)P * m);
+  D.held = cv.take<int32_t>(nt);
+  D.eterm = cv.take<double>(nt);
+  D.px = cv.take<double>(nt * R.splits);
+  D.py = cv.take<double>(nt * R.splits);
+  D.pe = cv.take<double>(nt * R.splits);
+  D.st = cv.take<PState>(P);
+  D.ptr_w = cv.take<int32_t>(P + 1);
+  D.ptol = cv.take<double>(P);
+  D.err = cv.take<int32_t>(1);
+  D.running = cv.take<int32_t>(1);
+  R.hcount = cv.take<int32_t>(P);
+  if (precision == CD_MIXED) {
+    D.fgx = cv.take<double>(nt);
+    D.fgy = cv.take<double>(nt);
+    D.fhxx = cv.take<double>(nt);
+    D.fhxy = cv.take<double>(nt);
+    D.fhyy = cv.take<double>(nt);
+    D.zrx = cv.take<double>(nt);
+    D.zry = cv.take<double>(nt);
+    D.hptr = cv.take<int32_t>(P + 1);
+    D.hidx = cv.take<int32_t>(R.hcap);
+    D.a32x = cv.take<float>(nt);
+    D.a32y = cv.take<float>(nt);
+    D.h32x = cv.take<float>(R.hcap);
+    D.h32y = cv.take<float>(R.hcap);
+    D.h64x = cv.take<double>(R.hcap);
+    D.h64y = cv.take<double>(R.hcap);
+  } else {
+    D.fgx = D.fgy = D.fhxx = D.fhxy = D.fhyy = D.zrx = D.zry = nullptr;
+    D.hptr = D.hidx = nullptr;
+    D.a32x = D.a32y = D.h32x = D.h32y = nullptr;
+    D.h64x = D.h64y = nullptr;
+  }
+  D.n = R.n;
+  D.P = P;
+  D.nbN = R.nbN;
+  D.m = m;
+  D.ntot = R.ntot;
+  D.splits = R.splits;
+  D.jb = R.jb;
+  D.hcap = R.hcap;
+  R.total = cv.off + 256;
+  return true;
+}
+
 size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total_active,
                              int precision) {
-  (void)op; (void)n; (void)n_patches; (void)total_active; (void)precision;
-  return 0;
+  if (op == CD_OP_PATCHES)
+    return n_patches > 0 ? (((size_t)n_patches + 2) * 4 + 511) & ~size_t(255) : 0;
+  if (op != CD_OP_RELAX) return 0;
+  RPlan R;
+  if (!rplan(n, n_patches, total_active, precision, kMaxMem, nullptr, R)) return 0;
+  return R.total;
 }
+
+// Runs rounds (eval + update) until no patch is running or max rounds.
+// Returns a CD status.
+static int g_last_rounds = 0;
+
+template <class EvalFn>
+static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, EvalFn eval) {
+  RelaxDev& D = R.D;
+  int32_t h_running = 0;
+  hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
+  for (int r = 0; r < max_rounds; ++r) {
+    g_last_rounds = r + 1;
+    eval();
+    hipLaunchKernelGGL(k_update, dim3(R.P), dim3(kUpd), 0, st, D);
+    if ((r & 7) == 7) {
+      if (hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+          hipSuccess)
+        return CD_ERR_HIP;
+      if (hipStreamSynchronize(st) != hipSuccess) return CD_ERR_HIP;
+      if (h_running <= 0) break;
+    }
+  }
+  return hip_status(hipGetLastError());
+}
+
 }  // namespace cd
+
+using namespace cd;
+
+extern "C" {
+
+int build_patches(const double* x, const double* y, int64_t n, int32_t n_patches,
+                  const int32_t* centres, const int32_t* patch_ptr, int32_t* active_idx, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!x || !y || !centres || !patch_ptr || !active_idx || n < 1 || n > (1 << 26) ||
+      n_patches < 1 || patch_ptr[0] != 0)
+    return CD_ERR_INVALID_ARG;
+  for (int p = 0; p < n_patches; ++p) {
+    const int sz = patch_ptr[p + 1] - patch_ptr[p];
+    if (sz < 1 || sz > n) return CD_ERR_INVALID_ARG;
+  }
+  if (!ws || ws_bytes < relax_workspace_bytes(CD_OP_PATCHES, n, n_patches, 0, 0))
+    return CD_ERR_WORKSPACE;
+  int32_t* ptr_d =
+      reinterpret_cast<int32_t*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  int32_t* err_d = ptr_d + n_patches + 1;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = hip_status(hipMemcpyAsync(ptr_d, patch_ptr, sizeof(int32_t) * (n_patches + 1),
+                                     hipMemcpyHostToDevice, st));
+  if (rc) return rc;
+  if ((rc = hip_status(hipMemsetAsync(err_d, 0, sizeof(int32_t), st)))) return rc;
+  hipLaunchKernelGGL(k_patch_select, dim3(n_patches), dim3(1024), 0, st, x, y, (int)n, centres,
+                     ptr_d, active_idx, err_d);
+  rc = hip_status(hipGetLastError());
+  if (rc) return rc;
+  int32_t herr = 0;
+  if ((rc = hip_status(hipMemcpyAsync(&herr, err_d, sizeof(int32_t), hipMemcpyDeviceToHost, st))))
+    return rc;
+  // also lets the caller release the host offsets array after return
+  if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+  return herr ? CD_ERR_INVALID_ARG : CD_OK;
+}
+
+int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patches,
+                     const int32_t* patch_ptr, const int32_t* active_idx, const double* x_start,
+                     const double* y_start, const cd_relax_opts* opts, double* x_out,
+                     double* y_out, double* dE, double* e_sub, double* gtan_inf, int32_t* iters,
+                     int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !y || !patch_ptr || !active_idx || !opts) return CD_ERR_INVALID_ARG;
+  if ((x_start == nullptr) != (y_start == nullptr)) return CD_ERR_INVALID_ARG;
+  if ((x_out == nullptr) != (y_out == nullptr)) return CD_ERR_INVALID_ARG;
+  if (n_patches < 1 || patch_ptr[0] != 0) return CD_ERR_INVALID_ARG;
+  for (int p = 0; p < n_patches; ++p)
+    if (patch_ptr[p + 1] <= patch_ptr[p] || patch_ptr[p + 1] - patch_ptr[p] > n)
+      return CD_ERR_INVALID_ARG;
+  const cd_relax_opts o = *opts;
+  if (!(o.gtol > 0.0) || o.max_iter < 0 || o.halo_width < 0.0 || o.inner_tol < 0.0 ||
+      o.step0 < 0.0 || o.max_outer < 0)
+    return CD_ERR_INVALID_ARG;
+  const int64_t ntot = patch_ptr[n_patches];
+  if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
+  const int m = o.lbfgs_m > 0 ? o.lbfgs_m : 8;
+  RPlan R;
+  if (!rplan(n, n_patches, ntot, o.precision, m, nullptr, R)) return CD_ERR_INVALID_ARG;
+  if (!ws) return CD_ERR_WORKSPACE;
+  if (ws_bytes < R.total) return CD_ERR_WORKSPACE;  // the plan actually used, memory m
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  rplan(n, n_patches, ntot, o.precision, m, base, R);
+  hipStream_t st = (hipStream_t)stream;
+  RelaxDev& D = R.D;
+  double* const ptol_ws = D.ptol;
+  D.ptol = nullptr;
+  D.x = x;
+  D.y = y;
+  D.ptr = D.ptr_w;
+  D.idx = active_idx;
+  const double h = sqrt(2.0 * 3.141592653589793 / (sqrt(3.0) * (double)n));
+  D.step0 = o.step0 > 0.0 ? o.step0 : 0.1 * h;
+  D.c1 = 1e-4;
+  D.noise_rel = 1e-14;
+  D.max_iter = o.max_iter;
+  D.eval_all = 0;
+  const int max_iter_eff = o.max_iter > 0 ? o.max_iter : 1;
+  const int max_rounds = 4 * max_iter_eff + 64;
+
+  std::vector<int2> blk;
+  blk.reserve(R.nblk);
+  for (int p = 0; p < n_patches; ++p)
+    for (int a = patch_ptr[p]; a < patch_ptr[p + 1]; a += 64) blk.push_back(make_int2(p, a));
+  D.nblk = (int)blk.size();
+  int rc;
+  if ((rc = hip_status(hipMemcpyAsync(D.ptr_w, patch_ptr, sizeof(int32_t) * (n_patches + 1),
+                                      hipMemcpyHostToDevice, st))))
+    return rc;
+  if ((rc = hip_status(hipMemcpyAsync(D.blk, blk.data(), blk.size() * sizeof(int2),
+                                      hipMemcpyHostToDevice, st))))
+    return rc;
+  if ((rc = hip_status(hipMemsetAsync(D.maskA, 0, sizeof(uint64_t) * n_patches * R.nbN, st))))
+    return rc;
+  if ((rc = hip_status(hipMemsetAsync(D.maskAH, 0, sizeof(uint64_t) * n_patches * R.nbN, st))))
+    return rc;
+  const int tb = (int)((ntot + 255) / 256);
+  if ((rc = hip_status(hipMemsetAsync(D.err, 0, sizeof(int32_t), st)))) return rc;
+  hipLaunchKernelGGL(k_setup_actives, dim3(tb), dim3(256), 0, st, D, x_start, y_start);
+  {
+    int32_t herr = 0;
+    if ((rc = hip_status(hipMemcpyAsync(&herr, D.err, sizeof(int32_t), hipMemcpyDeviceToHost, st))))
+      return rc;
+    if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+    if (herr) return CD_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_patch_geom, dim3(n_patches), dim3(256), 0, st, D);
+  const dim3 eg((D.nblk + 3) / 4, R.splits), eb(256);
+  auto exact_grad = [&](int all) {
+    RelaxDev E = D;
+    E.eval_all = all;
+    hipLaunchKernelGGL(k_exact<kGrad>, eg, eb, 0, st, E);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb), dim3(256), 0, st, E, 1);
+  };
+
+  if (o.precision == CD_FP64) {
+    D.tol = o.gtol;
+    if ((rc = run_rounds(R, st, max_rounds, [&]() { exact_grad(0); }))) return rc;
+  } else {
+    const double w = (o.halo_width > 0.0 ? o.halo_width : 4.0) * h;
+    hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 0, R.hcount);
+    std::vector<int32_t> hc(n_patches), hp(n_patches + 1);
+    if ((rc = hip_status(hipMemcpyAsync(hc.data(), R.hcount, sizeof(int32_t) * n_patches,
+                                        hipMemcpyDeviceToHost, st))))
+      return rc;
+    if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+    hp[0] = 0;
+    for (int p = 0; p < n_patches; ++p) hp[p + 1] = hp[p] + hc[p];
+    if (hp[n_patches] > R.hcap) return CD_ERR_WORKSPACE;
+    if ((rc = hip_status(hipMemcpyAsync(D.hptr, hp.data(), sizeof(int32_t) * (n_patches + 1),
+                                        hipMemcpyHostToDevice, st))))
+      return rc;
+    hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 1, R.hcount);
+    RelaxDev Df = D;
+    Df.splits = 1;
+    Df.jb = R.nbN;
+    Df.eval_all = 1;
+    const int hb = (hp[n_patches] + 255) / 256;
+    hipLaunchKernelGGL(k_model_prep, dim3(tb > hb ? tb : hb), dim3(256), 0, st, D, 1);
+    auto model = [&](int all) {
+      RelaxDev E = D;
+      E.eval_all = all;
+      hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
+      hipLaunchKernelGGL(k_model, dim3((D.nblk + 3) / 4), eb, 0, st, E);
+    };
+    // rounds: expand the far field exactly at z (one O(n_act N) FP64 pass);
+    // the model gradient at its expansion point is the exact gradient, which
+    // ends a patch when it meets gtol; otherwise minimise the model (FP32
+    // pairs while the exact gradient is above tol32, FP64 pairs below) to a
+    // hundredth of it, keeping the L-BFGS history across rounds
+    const double tol32 = o.inner_tol > 0.0 ? o.inner_tol : 3e-2 / (h * h);
+    const int outer_max = o.max_outer > 0 ? o.max_outer : 40;
+    const bool trace = getenv("CD_RELAX_TRACE") != nullptr;
+    for (int outer = 0; outer < outer_max; ++outer) {
+      hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
+      hipLaunchKernelGGL(k_exact<kFar>, dim3((D.nblk + 3) / 4, 1), eb, 0, st, Df);
+      model(1);
+      hipLaunchKernelGGL(k_check, dim3(n_patches), dim3(kUpd), 0, st, D, o.gtol, 0.01, tol32,
+                         ptol_ws);
+      hipLaunchKernelGGL(k_restart, dim3((n_patches + 255) / 256), dim3(256), 0, st, D, outer > 0);
+      hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
+      int32_t hr = 0;
+      if ((rc = hip_status(hipMemcpyAsync(&hr, D.running, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                          st))))
+        return rc;
+      if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+      if (trace) {
+        std::vector<PState> hs(n_patches);
+        (void)hipMemcpy(hs.data(), D.st, sizeof(PState) * n_patches, hipMemcpyDeviceToHost);
+        double gmax = 0.0;
+        long its = 0;
+        int n32 = 0, nd = 0;
+        for (const PState& q : hs) {
+          gmax = fmax(gmax, q.gi);
+          its += q.total_it;
+          n32 += q.use32 && q.status == kRunning;
+          nd += q.status == kDone;
+        }
+        fprintf(stderr,
+                "[relax] round %d: running %d (fp32 %d) done %d, exact gi max %.3e, iterations so "
+                "far %ld, lock-step rounds last stage %d\n",
+                outer, hr, n32, nd, gmax, its, g_last_rounds);
+      }
+      if (hr == 0) break;
+      D.ptol = ptol_ws;
+      rc = run_rounds(R, st, max_rounds, [&]() { model(0); });
+      D.ptol = nullptr;
+      if (rc) return rc;
+    }
+  }
+  // exact energy and reduced gradient at the final positions, then the exact
+  // energy change from the snapshot
+  hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
+  exact_grad(1);
+  hipLaunchKernelGGL(k_finish, dim3(n_patches), dim3(kUpd), 0, st, D, o.gtol,
+                     o.precision == CD_FP64 ? 1 : 0, x_out, y_out, e_sub, gtan_inf, iters, status);
+  if (dE) {
+    hipLaunchKernelGGL(k_exact<kDelta>, eg, eb, 0, st, D);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb), dim3(256), 0, st, D, 0);
+    hipLaunchKernelGGL(k_finish_delta, dim3(n_patches), dim3(kUpd), 0, st, D, dE);
+  }
+  rc = hip_status(hipGetLastError());
+  if (rc) return rc;
+  return hip_status(hipStreamSynchronize(st));
+}
+
+}  // extern "C"

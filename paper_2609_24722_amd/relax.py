@@ -1,0 +1,114 @@
+"""ctypes binding of the subdomain entry points (build_patches,
+relax_subdomains): argument marshalling only.
+
+A batch of P patches is given by host offsets ``ptr`` (numpy int32, length
+P+1) and a device int32 tensor of charge indices (packed per patch).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import FP64, MIXED
+from . import ops
+
+_vp = ctypes.c_void_p
+
+
+class RelaxOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("lbfgs_m", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32),
+        ("gtol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
+        ("halo_width", ctypes.c_double),
+        ("step0", ctypes.c_double),
+    ]
+
+
+def _bind(L):
+    L.build_patches.restype = ctypes.c_int
+    L.build_patches.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                ctypes.c_size_t, _vp]
+    L.relax_subdomains.restype = ctypes.c_int
+    L.relax_subdomains.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                   ctypes.POINTER(RelaxOpts), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, ctypes.c_size_t, _vp]
+
+
+def offsets(sizes) -> np.ndarray:
+    sizes = np.asarray(sizes, dtype=np.int64)
+    ptr = np.zeros(sizes.size + 1, dtype=np.int32)
+    ptr[1:] = np.cumsum(sizes)
+    return ptr
+
+
+def build_patches(x, y, centres, sizes):
+    """The sizes[p] charges nearest to charge centres[p] (Sec. II.C steps 3-4),
+    per patch in increasing index order.  Returns (ptr host int32, idx device)."""
+    dev = ops._chk(x, y)
+    n = x.numel()
+    ptr = offsets(sizes)
+    c = torch.as_tensor(np.asarray(centres, dtype=np.int32), device=dev)
+    idx = torch.empty(int(ptr[-1]), dtype=torch.int32, device=dev)
+    ws, nb = ops.workspace(ops.OP_PATCHES, n, ops.FP64, dev, n_patches=ptr.size - 1)
+    ops.check(ops.lib().build_patches(x.data_ptr(), y.data_ptr(), n, ptr.size - 1, c.data_ptr(),
+                                      ptr.ctypes.data, idx.data_ptr(), ws.data_ptr(), nb,
+                                      ops.stream_ptr(dev)), "build_patches")
+    return ptr, idx
+
+
+@dataclass
+class RelaxResult:
+    x: torch.Tensor        # packed relaxed positions
+    y: torch.Tensor
+    dE: torch.Tensor       # [P] E_sub(relaxed) - E_sub(snapshot), exact FP64
+    e_sub: torch.Tensor    # [P] exact E_sub at the relaxed positions
+    gtan_inf: torch.Tensor  # [P] exact reduced-gradient inf-norm
+    iters: torch.Tensor    # [P, 2] L-BFGS iterations, exact evaluations
+    status: torch.Tensor   # [P] 0 converged, 1 cap, 2 line search failed, 3 non-finite
+
+
+def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
+                     max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
+                     step0=0.0) -> RelaxResult:
+    """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
+
+    max_iter defaults to 300 per round for the mixed path and 8000 in total for
+    the FP64 path."""
+    if max_iter is None:
+        max_iter = 300 if precision == MIXED else 8000
+    dev = ops._chk(x, y)
+    n = x.numel()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    P = ptr.size - 1
+    ntot = int(ptr[-1])
+    if idx.dtype != torch.int32 or idx.numel() != ntot or idx.device != dev:
+        raise ops.CoulombError("idx must be a device int32 tensor of length ptr[-1]")
+    if x_start is not None:
+        ops._chk(x_start, y_start)
+        if x_start.numel() != ntot:
+            raise ops.CoulombError("start positions must be packed like idx")
+    o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), int(max_outer), float(gtol),
+                  float(inner_tol), float(halo_width), float(step0))
+    f = dict(dtype=torch.float64, device=dev)
+    xo = torch.empty(ntot, **f)
+    yo = torch.empty(ntot, **f)
+    dE = torch.empty(P, **f)
+    es = torch.empty(P, **f)
+    gt = torch.empty(P, **f)
+    it = torch.empty((P, 2), dtype=torch.int32, device=dev)
+    stt = torch.empty(P, dtype=torch.int32, device=dev)
+    ws, nb = ops.workspace(ops.OP_RELAX, n, int(precision), dev, n_patches=P, total_active=ntot)
+    ops.check(ops.lib().relax_subdomains(
+        x.data_ptr(), y.data_ptr(), n, P, ptr.ctypes.data, idx.data_ptr(),
+        x_start.data_ptr() if x_start is not None else None,
+        y_start.data_ptr() if y_start is not None else None, ctypes.byref(o),
+        xo.data_ptr(), yo.data_ptr(), dE.data_ptr(), es.data_ptr(), gt.data_ptr(), it.data_ptr(),
+        stt.data_ptr(), ws.data_ptr(), nb, ops.stream_ptr(dev)), "relax_subdomains")
+    return RelaxResult(xo, yo, dE, es, gt, it, stt)

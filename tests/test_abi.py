@@ -31,7 +31,7 @@ def L():
 
 def test_header_declares_entry_points():
     names = declared_functions()
-    for n in ["coulomb_energy", "coulomb_forces", "coulomb_hvp",
+    for n in ["coulomb_energy", "coulomb_forces", "coulomb_hvp", "relax_subdomains", "build_patches",
               "coulomb_workspace_bytes", "coulomb_validate", "coulomb_status_string"]:
         assert n in names, n
 
@@ -65,3 +65,33 @@ def test_argument_errors_before_any_launch(L):
     assert L.coulomb_forces(fake, fake, 0, 0, fake, fake, None, fake, 1 << 30, None) == -1
     L.coulomb_status_string.restype = ctypes.c_char_p
     assert L.coulomb_status_string(-2) == b"workspace missing or too small"
+
+
+def test_relax_argument_errors_before_any_launch(L):
+    import numpy as np
+
+    class Opts(ctypes.Structure):
+        _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
+                    ("max_outer", ctypes.c_int32), ("gtol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                    ("halo_width", ctypes.c_double), ("step0", ctypes.c_double)]
+    vp = ctypes.c_void_p
+    f = L.relax_subdomains
+    f.restype = ctypes.c_int
+    f.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp, vp,
+                  vp, vp, vp, ctypes.c_size_t, vp]
+    ws = L.coulomb_workspace_bytes
+    ws.restype = ctypes.c_size_t
+    ws.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int]
+    ptr = np.array([0, 10, 30], dtype=np.int32)
+    fake = vp(256)
+    big = ws(5, 1000, 2, 30, 1)
+    assert big > 0 and ws(5, 1000, 2, 30, 0) > 0
+    o = Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0)
+    call = lambda o, wsb, p=ptr: f(fake, fake, 1000, 2, p.ctypes.data, fake, None, None, ctypes.byref(o),
+                                   fake, fake, None, None, None, None, None, fake, wsb, None)
+    assert call(Opts(1, 100, 17, 0, 1e-3, 0.0, 0.0, 0.0), big) == -1   # memory above 16
+    assert call(Opts(1, 100, 8, 0, 0.0, 0.0, 0.0, 0.0), big) == -1     # gtol must be > 0
+    assert call(Opts(3, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0), big) == -1    # bad precision
+    assert call(o, 1024) == -2                                          # workspace too small
+    assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
+    assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0

@@ -302,3 +302,23 @@ def test_rows_match_full_sums():
     a, b, _ = O.rows(x, y, r, vx, vy)
     np.testing.assert_array_equal(a, hx[r])
     np.testing.assert_array_equal(b, hy[r])
+
+
+def test_patches_definition():
+    # every selected charge precedes every unselected one in (squared distance,
+    # index) order, the selection has the requested size and is index-sorted
+    x, y = random_config(500, 23)
+    centres = np.array([0, 17, 499], dtype=np.int32)
+    sizes = np.array([1, 40, 500], dtype=np.int32)
+    out = O.patches(x, y, centres, sizes)
+    off = 0
+    for c, k in zip(centres, sizes):
+        sel = out[off:off + k]
+        off += k
+        assert sel.size == k and np.all(np.diff(sel) > 0) and c in sel
+        d2 = (x - x[c]) * (x - x[c]) + (y - y[c]) * (y - y[c])
+        rest = np.setdiff1d(np.arange(x.size), sel)
+        if rest.size:
+            worst_in = max(zip(d2[sel], sel))
+            best_out = min(zip(d2[rest], rest))
+            assert worst_in < best_out
