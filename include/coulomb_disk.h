@@ -154,6 +154,44 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                      double* gtan_inf, int32_t* iters, int32_t* status, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
+ * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE
+ * of relax_subdomains) is negative are visited in increasing order of it
+ * (ties by index).  A candidate sharing a charge with one already committed
+ * is skipped; otherwise its exact FP64 energy change is evaluated again
+ * against the current configuration and, iff negative, its packed positions
+ * x_rel, y_rel (device) are written into x, y (device, updated in place).
+ * committed[P] (host int32): 1 if committed; dE_commit[P] (host): the
+ * re-evaluated change (0 when not evaluated).  ws: at least
+ * coulomb_workspace_bytes(CD_OP_RELAX, n, 1, largest patch, CD_FP64) + 512
+ * bytes.  Synchronises the stream. */
+int commit_patches(double* x, double* y, int64_t n, int32_t n_patches, const int32_t* patch_ptr,
+                   const int32_t* active_idx, const double* x_rel, const double* y_rel,
+                   const double* order_key, int32_t* committed, double* dE_commit, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Local-minimum certificate (tangent space of the hard wall of Eq. 3):
+ * k steps of Lanczos with full reorthogonalisation on the operator
+ *   H_t v = P H P v + w o v,
+ * H the Hessian of the energy (of E_sub over the active charges when mask is
+ * given), P the projection removing the radial component of held charges
+ * (|r| >= 1 - 1e-14 with outward force F . r_hat > 0) and every component of
+ * inactive ones, w_i = F_i . r_hat_i on held charges (the circle's curvature
+ * term), 0 elsewhere.  FP64 Hessian-vector products throughout.
+ *   mask: device int32 [n], nonzero = active, or NULL (all active).
+ *   k: 2..4096 Lanczos steps (lanczos_k, passed as n_patches to
+ *      coulomb_workspace_bytes(CD_OP_LANCZOS, n, k, 0, 0)).
+ *   deflate_rotation: nonzero projects out the rigid rotation (-y, x), an
+ *      exact zero mode of a full-disk configuration.
+ *   seed: start vector (counter-based hash, uniform in [-1, 1)).
+ *   out_host[4] (host): smallest Ritz value theta, residual ||H_t u - theta u||
+ *      of its unit Ritz vector, largest Ritz value, steps used.
+ * A positive theta with residual below theta/2 certifies a strict local
+ * minimum.  Synchronises the stream before returning. */
+int tangent_lanczos(const double* x, const double* y, int64_t n, const int32_t* mask,
+                    int32_t k, int32_t deflate_rotation, uint64_t seed, double* out_host,
+                    void* ws, size_t ws_bytes, void* stream);
+
 /* Measurement hook: when ev_start/ev_stop (hipEvent_t passed as void*) are
  * non-NULL, every later energy/forces/HVP call records ev_start immediately
  * before and ev_stop immediately after its dominant pair kernel, on the

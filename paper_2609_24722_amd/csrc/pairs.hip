@@ -11,7 +11,7 @@
 //                  CD_FP64: one-sided FP64 kernel over (i block, j range);
 //   3. reduction   fixed-order sums of the partial results, scattered back
 //                  to the caller's order; energy by a fixed-shape tree.
-#include "common.hpp"
+#include "plan.hpp"
 
 namespace cd {
 
@@ -56,14 +56,14 @@ __global__ void k_gather(const double* __restrict__ x, const double* __restrict_
     int p = perm[s];
     xs[s] = x[p];
     ys[s] = y[p];
-    if (vxs) {
+    if (vxs && vx) {  // v is gathered only when given (staged HVPs gather it per call)
       vxs[s] = vx[p];
       vys[s] = vy[p];
     }
   } else {
     xs[s] = pad_x(s - n);
     ys[s] = 0.0;
-    if (vxs) {
+    if (vxs && vx) {
       vxs[s] = 0.0;
       vys[s] = 0.0;
     }
@@ -604,24 +604,7 @@ __global__ void k_validate(const double* __restrict__ xs, const double* __restri
 }
 
 // ---------------------------------------------------------------- planning --
-struct Plan {
-  int n = 0, npad = 0, nb = 0;
-  int W = 0, L = 0, C = 0, G = 0, S = 0;  // symmetric pass
-  int splits = 0, jb = 0;                 // one-sided pass
-  int nred = 0;                           // reduction workgroups
-  // workspace pieces
-  uint32_t *keys = nullptr, *keys2 = nullptr, *hist = nullptr;
-  int32_t *perm = nullptr, *perm2 = nullptr;
-  double *xs = nullptr, *ys = nullptr, *vxs = nullptr, *vys = nullptr;
-  double* cen = nullptr;
-  float* box = nullptr;
-  double *q0 = nullptr, *q1 = nullptr, *q2 = nullptr;  // i partials / one-sided partials
-  double *j0 = nullptr, *j1 = nullptr;                 // j partials
-  double* eblk = nullptr;
-  size_t total = 0;
-};
-
-static bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
+bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
   if (n64 < 1 || n64 > (int64_t)1 << 26) return false;
   if (precision != CD_FP64 && precision != CD_MIXED) return false;
   const int n = (int)n64;
@@ -677,7 +660,7 @@ static bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
   return true;
 }
 
-static int stage(const Plan& P, const double* x, const double* y, const double* vx,
+int stage(const Plan& P, const double* x, const double* y, const double* vx,
                  const double* vy, hipStream_t st) {
   const int n = P.n;
   hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, st, x, y, n, P.keys,
@@ -778,8 +761,45 @@ static void run_one64(const Plan& P, hipStream_t st, double* out0, double* out1)
   hipLaunchKernelGGL((k_one64_reduce<MODE>), dim3(P.nred), dim3(256), 0, st, r);
 }
 
+
+// v in caller order -> sorted, padded copies (pads carry v = 0)
+__global__ void k_gather_v(const double* __restrict__ vx, const double* __restrict__ vy,
+                           const int32_t* __restrict__ perm, int n, int npad,
+                           double* __restrict__ vxs, double* __restrict__ vys) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= npad) return;
+  if (s < n) {
+    const int p = perm[s];
+    vxs[s] = vx[p];
+    vys[s] = vy[p];
+  } else {
+    vxs[s] = 0.0;
+    vys[s] = 0.0;
+  }
+}
+
+size_t hvp64_bytes(int64_t n) {
+  Plan P;
+  return make_plan(CD_OP_HVP, n, CD_FP64, nullptr, P) ? P.total : 0;
+}
+
+int hvp64_stage(Plan& P, char* base, int64_t n, const double* x, const double* y,
+                hipStream_t st) {
+  if (!make_plan(CD_OP_HVP, n, CD_FP64, base, P)) return CD_ERR_INVALID_ARG;
+  return stage(P, x, y, nullptr, nullptr, st);
+}
+
+int hvp64_apply(const Plan& P, const double* vx, const double* vy, double* hx, double* hy,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_v, dim3((P.npad + 255) / 256), dim3(256), 0, st, vx, vy, P.perm,
+                     P.n, P.npad, P.vxs, P.vys);
+  run_one64<kHvp>(P, st, hx, hy);
+  return hip_status(hipGetLastError());
+}
+
 size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total_active,
                              int precision);
+size_t lanczos_workspace_bytes(int64_t n, int k);
 
 }  // namespace cd
 
@@ -796,6 +816,7 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
     if (!make_plan(op, n, op == CD_OP_VALIDATE ? CD_FP64 : precision, nullptr, P)) return 0;
     return P.total;
   }
+  if (op == CD_OP_LANCZOS) return cd::lanczos_workspace_bytes(n, n_patches);
   return cd::relax_workspace_bytes(op, n, n_patches, total_active, precision);
 }
 

@@ -32,6 +32,7 @@
 // workgroup per patch.
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -1215,6 +1216,7 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 // Runs rounds (eval + update) until no patch is running or max rounds.
 // Returns a CD status.
 static int g_last_rounds = 0;
+static bool g_trace = false;  // CD_RELAX_TRACE set: progress lines on stderr
 
 template <class EvalFn>
 static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, EvalFn eval) {
@@ -1231,6 +1233,7 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, EvalFn eval) {
         return CD_ERR_HIP;
       if (hipStreamSynchronize(st) != hipSuccess) return CD_ERR_HIP;
       if (h_running <= 0) break;
+      if (g_trace && (r & 255) == 255) fprintf(stderr, "[relax] lock-step round %d: %d running\n", r + 1, h_running);
     }
   }
   return hip_status(hipGetLastError());
@@ -1274,6 +1277,16 @@ int build_patches(const double* x, const double* y, int64_t n, int32_t n_patches
   return herr ? CD_ERR_INVALID_ARG : CD_OK;
 }
 
+// scatter of committed positions: x[idx[a]] = xr[a]
+__global__ void k_scatter(double* __restrict__ x, double* __restrict__ y,
+                          const int32_t* __restrict__ idx, const double* __restrict__ xr,
+                          const double* __restrict__ yr, int m) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= m) return;
+  x[idx[a]] = xr[a];
+  y[idx[a]] = yr[a];
+}
+
 int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patches,
                      const int32_t* patch_ptr, const int32_t* active_idx, const double* x_start,
                      const double* y_start, const cd_relax_opts* opts, double* x_out,
@@ -1312,6 +1325,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   D.c1 = 1e-4;
   D.noise_rel = 1e-14;
   D.max_iter = o.max_iter;
+  g_trace = getenv("CD_RELAX_TRACE") != nullptr;
   D.eval_all = 0;
   const int max_iter_eff = o.max_iter > 0 ? o.max_iter : 1;
   const int max_rounds = 4 * max_iter_eff + 64;
@@ -1388,7 +1402,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     // hundredth of it, keeping the L-BFGS history across rounds
     const double tol32 = o.inner_tol > 0.0 ? o.inner_tol : 3e-2 / (h * h);
     const int outer_max = o.max_outer > 0 ? o.max_outer : 40;
-    const bool trace = getenv("CD_RELAX_TRACE") != nullptr;
+    const bool trace = g_trace;
     for (int outer = 0; outer < outer_max; ++outer) {
       hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
       hipLaunchKernelGGL(k_exact<kFar>, dim3((D.nblk + 3) / 4, 1), eb, 0, st, Df);
@@ -1439,6 +1453,80 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   }
   rc = hip_status(hipGetLastError());
   if (rc) return rc;
+  return hip_status(hipStreamSynchronize(st));
+}
+
+// Greedy commit of relaxed candidates.  Candidates with a negative energy
+// change at the snapshot are visited in increasing order of that change
+// (ties by index); one that shares a charge with an already committed
+// candidate is skipped; otherwise its energy change is evaluated again,
+// exactly, against the current configuration (earlier commits included,
+// since the 1/r coupling makes changes non-additive) and it is committed --
+// its positions written into x, y -- iff that change is negative.
+int commit_patches(double* x, double* y, int64_t n, int32_t n_patches, const int32_t* patch_ptr,
+                   const int32_t* active_idx, const double* x_rel, const double* y_rel,
+                   const double* order_key, int32_t* committed, double* dE_commit, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!x || !y || !patch_ptr || !active_idx || !x_rel || !y_rel || !order_key || !committed ||
+      !dE_commit || n_patches < 1 || patch_ptr[0] != 0)
+    return CD_ERR_INVALID_ARG;
+  int maxp = 0;
+  for (int p = 0; p < n_patches; ++p) {
+    const int sz = patch_ptr[p + 1] - patch_ptr[p];
+    if (sz < 1 || sz > n) return CD_ERR_INVALID_ARG;
+    maxp = sz > maxp ? sz : maxp;
+  }
+  const size_t need = relax_workspace_bytes(CD_OP_RELAX, n, 1, maxp, CD_FP64);
+  if (!need) return CD_ERR_INVALID_ARG;
+  if (!ws) return CD_ERR_WORKSPACE;
+  if (ws_bytes < need + 512) return CD_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const int ntot = patch_ptr[n_patches];
+  std::vector<int32_t> idx(ntot);
+  int rc = hip_status(hipMemcpyAsync(idx.data(), active_idx, sizeof(int32_t) * ntot,
+                                     hipMemcpyDeviceToHost, st));
+  if (rc) return rc;
+  if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+  for (int a = 0; a < ntot; ++a)
+    if (idx[a] < 0 || idx[a] >= n) return CD_ERR_INVALID_ARG;
+  std::vector<int> order;
+  for (int p = 0; p < n_patches; ++p) {
+    committed[p] = 0;
+    dE_commit[p] = 0.0;
+    if (order_key[p] < 0.0) order.push_back(p);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return order_key[a] < order_key[b]; });
+  std::vector<unsigned char> taken(n, 0);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  double* dEd = reinterpret_cast<double*>(base);
+  char* rws = base + 256;
+  cd_relax_opts o = {};
+  o.precision = CD_FP64;
+  o.max_iter = 0;  // evaluation only: energy change of the given positions
+  o.gtol = 1e300;
+  for (int p : order) {
+    const int a0 = patch_ptr[p], a1 = patch_ptr[p + 1];
+    bool clash = false;
+    for (int a = a0; a < a1 && !clash; ++a) clash = taken[idx[a]];
+    if (clash) continue;
+    const int32_t pp[2] = {0, a1 - a0};
+    rc = relax_subdomains(x, y, n, 1, pp, active_idx + a0, x_rel + a0, y_rel + a0, &o, nullptr,
+                          nullptr, dEd, nullptr, nullptr, nullptr, nullptr, rws, need, stream);
+    if (rc) return rc;
+    double d = 0.0;
+    if ((rc = hip_status(hipMemcpyAsync(&d, dEd, sizeof(double), hipMemcpyDeviceToHost, st))))
+      return rc;
+    if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+    dE_commit[p] = d;
+    if (d < 0.0) {
+      hipLaunchKernelGGL(k_scatter, dim3((a1 - a0 + 255) / 256), dim3(256), 0, st, x, y,
+                         active_idx + a0, x_rel + a0, y_rel + a0, a1 - a0);
+      if ((rc = hip_status(hipGetLastError()))) return rc;
+      committed[p] = 1;
+      for (int a = a0; a < a1; ++a) taken[idx[a]] = 1;
+    }
+  }
   return hip_status(hipStreamSynchronize(st));
 }
 

@@ -146,3 +146,26 @@ def validate(x, y):
     check(lib().coulomb_validate(x.data_ptr(), y.data_ptr(), n, flags.data_ptr(), cnt.data_ptr(),
                                  ws.data_ptr(), nb, stream_ptr(dev)), "coulomb_validate")
     return flags, cnt
+
+
+def tangent_lanczos(x, y, k: int = 200, mask=None, deflate_rotation: bool = True, seed: int = 12345):
+    """Smallest and largest Ritz values of the tangent-space Hessian (hard
+    wall of Eq. 3) after k Lanczos steps, with the residual of the smallest.
+    Returns dict(theta_min, resid, theta_max, steps, certified)."""
+    dev = _chk(x, y)
+    n = x.numel()
+    if mask is not None and (mask.dtype != torch.int32 or mask.numel() != n or mask.device != dev):
+        raise CoulombError("mask must be a device int32 tensor of length n")
+    L = lib()
+    if not getattr(L, "_lz_bound", False):
+        L.tangent_lanczos.restype = ctypes.c_int
+        L.tangent_lanczos.argtypes = [_vp, _vp, _i64, _vp, _i32, _i32, ctypes.c_uint64, _vp, _vp, _sz, _vp]
+        L._lz_bound = True
+    ws, nb = workspace(OP_LANCZOS, n, FP64, dev, n_patches=int(k))
+    out = (ctypes.c_double * 4)()
+    check(L.tangent_lanczos(x.data_ptr(), y.data_ptr(), n, mask.data_ptr() if mask is not None else None,
+                            int(k), int(bool(deflate_rotation)), int(seed), ctypes.cast(out, _vp),
+                            ws.data_ptr(), nb, stream_ptr(dev)), "tangent_lanczos")
+    th, res, tmax, steps = out[0], out[1], out[2], int(out[3])
+    return {"theta_min": th, "resid": res, "theta_max": tmax, "steps": steps,
+            "certified": bool(th > 0 and res < 0.5 * th)}

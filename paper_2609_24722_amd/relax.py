@@ -32,6 +32,9 @@ class RelaxOpts(ctypes.Structure):
 
 
 def _bind(L):
+    L.commit_patches.restype = ctypes.c_int
+    L.commit_patches.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, ctypes.c_size_t, _vp]
     L.build_patches.restype = ctypes.c_int
     L.build_patches.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp,
                                 ctypes.c_size_t, _vp]
@@ -112,3 +115,23 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
         xo.data_ptr(), yo.data_ptr(), dE.data_ptr(), es.data_ptr(), gt.data_ptr(), it.data_ptr(),
         stt.data_ptr(), ws.data_ptr(), nb, ops.stream_ptr(dev)), "relax_subdomains")
     return RelaxResult(xo, yo, dE, es, gt, it, stt)
+
+
+def commit_patches(x, y, ptr, idx, x_rel, y_rel, order_key):
+    """Greedy commit (see coulomb_disk.h): updates x, y in place; returns
+    (committed host int32 [P], dE_commit host float64 [P])."""
+    dev = ops._chk(x, y)
+    n = x.numel()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    P = ptr.size - 1
+    key = np.ascontiguousarray(order_key, dtype=np.float64)
+    com = np.zeros(P, dtype=np.int32)
+    dc = np.zeros(P, dtype=np.float64)
+    maxp = int(np.max(np.diff(ptr)))
+    need = int(ops.lib().coulomb_workspace_bytes(ops.OP_RELAX, n, 1, maxp, FP64)) + 512
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ops.check(ops.lib().commit_patches(x.data_ptr(), y.data_ptr(), n, P, ptr.ctypes.data, idx.data_ptr(),
+                                       x_rel.data_ptr(), y_rel.data_ptr(), key.ctypes.data, com.ctypes.data,
+                                       dc.ctypes.data, ws.data_ptr(), need, ops.stream_ptr(dev)),
+              "commit_patches")
+    return com, dc
