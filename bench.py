@@ -13,7 +13,17 @@ Printed: one JSON line with the driver's fields plus
   cpu_baseline  the CPU oracle on a bounded sample of rows of the same input;
   extra         FP64 energy+forces, HVP (both precisions) and energy-only rates.
 
+  relax         the batched subdomain relax of 256 patches (sizes U{200..5000})
+                on the same configuration, mixed path, seconds per batch ("cycle");
+                and mixed vs plain FP64 on the first 64 of those patches with the
+                per-patch energy agreement (same minimum: E_sub to 1e-12).
+
+Other modes: --cycles K runs K perturb-and-relax cycles (64 kicked patches
+each, greedy commit) and prints energy versus wall time; --copy-probe runs a
+plain device copy of known size (to calibrate HBM byte counters).
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
+                       [--no-relax] [--cycles K --cycle-n N] [--copy-probe]
 """
 import argparse
 import ctypes
@@ -76,24 +86,105 @@ def timed(fn, steps, warmup, lib, hip):
 
 
 def cpu_baseline(x, y, seconds=15.0):
-    """The oracle's E+F sums on a bounded sample of rows of the same input."""
+    """The oracle's E+F sums (every row against all N) on the same input,
+    repeated over row blocks until about `seconds` of CPU work is done."""
     import numpy as np
     import oracle as O
     n = x.size
-    rows = np.arange(0, n, max(1, n // 200), dtype=np.int32)
+    block = np.arange(0, n, max(1, n // 2000), dtype=np.int32)  # an even spread of rows
+    rows_done = 0
     t = time.perf_counter()
-    O.rows(x, y, rows)
+    k = 0
+    while time.perf_counter() - t < seconds:
+        O.rows(x, y, (block + k) % n)
+        rows_done += block.size
+        k += 1
     dt = time.perf_counter() - t
-    rate = rows.size * (n - 1) / dt
-    m = int(min(n, max(rows.size, seconds * rate / (n - 1))))
-    rows = np.linspace(0, n - 1, m).astype(np.int32)
-    t = time.perf_counter()
-    O.rows(x, y, rows)
-    dt = time.perf_counter() - t
-    return {"value": rows.size * (n - 1) / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
+    return {"value": rows_done * (n - 1) / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"{rows.size} of {n} charges (rows spread evenly), each against all {n - 1} others: "
-                      f"FP64 Neumaier sums of 1/r and (r_i - r_j)/r^3, {dt:.1f} s"}
+            "sample": f"{rows_done} rows (blocks of {block.size} evenly spread charges) of the N={n} input, "
+                      f"each against all {n - 1} others: FP64 Neumaier sums of 1/r and (r_i - r_j)/r^3, "
+                      f"{dt:.1f} s on {O.num_threads()} threads"}
+
+
+def relax_comparison(xt, yt, subset):
+    """Workload 4: 256 patches, sizes U{200..5000}, centres seeded, start at the
+    snapshot; gtol 1e-3 on the exact reduced gradient."""
+    import numpy as np
+    import torch
+    from paper_2609_24722_amd import FP64, MIXED, workloads as W
+    from paper_2609_24722_amd import relax as R
+    n = xt.numel()
+    centres, sizes = W.patch_draws(n, 256, 200, 5000, 1104)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+
+    def run(pp, ii, prec):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = R.relax_subdomains(xt, yt, pp, ii, precision=prec, gtol=1e-3)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    t_all, r_all = run(ptr, idx, MIXED)
+    ps = ptr[:subset + 1].copy()
+    ids = idx[:int(ps[-1])].contiguous()
+    t_mix, r_mix = run(ps, ids, MIXED)
+    t_fp, r_fp = run(ps, ids, FP64)
+    h = W.spacing(n)
+    em, ef = r_mix.e_sub.cpu().numpy(), r_fp.e_sub.cpu().numpy()
+    xm, ym, xf, yf = (a.cpu().numpy() for a in (r_mix.x, r_mix.y, r_fp.x, r_fp.y))
+    disp = np.array([np.hypot(xm[ps[p]:ps[p + 1]] - xf[ps[p]:ps[p + 1]],
+                              ym[ps[p]:ps[p + 1]] - yf[ps[p]:ps[p + 1]]).max() for p in range(subset)])
+    same = disp < 1e-3 * h
+    rel = np.abs(em - ef) / np.abs(ef)
+    st = lambda r: np.bincount(r.status.cpu().numpy(), minlength=4).tolist()
+    return {
+        "workload": f"N={n} warped lattice (sigma 0.02 h); 256 patches of the k nearest charges to "
+                    f"seeded centres, k ~ U{{200..5000}} (total {int(ptr[-1])} actives); start = snapshot; "
+                    f"gtol 1e-3 on the exact FP64 reduced gradient",
+        "mixed_s_per_cycle_256": t_all,
+        "mixed_status_256": st(r_all),
+        "mixed_exact_passes_mean_256": float(r_all.iters[:, 1].float().mean().item()),
+        "subset_patches": subset,
+        "subset_mixed_s": t_mix,
+        "subset_fp64_s": t_fp,
+        "subset_speedup": t_fp / t_mix,
+        "subset_status_mixed": st(r_mix),
+        "subset_status_fp64": st(r_fp),
+        "same_minimum_patches": int(same.sum()),
+        "same_minimum_max_rel_energy_diff": float(rel[same].max()) if same.any() else None,
+        "all_patches_median_rel_energy_diff": float(np.median(rel)),
+        "mean_dE_mixed": float(r_mix.dE.mean().item()),
+        "mean_dE_fp64": float(r_fp.dE.mean().item()),
+    }
+
+
+def copy_probe(dev):
+    """A plain device-to-device copy of 512 MiB, three times (for counters)."""
+    import torch
+    a = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": a.numel() * 8,
+                      "copy_probe_bytes_written_per_launch": a.numel() * 8}), flush=True)
+
+
+def cycles_mode(dev, cycles, n):
+    import torch
+    from paper_2609_24722_amd import workloads as W
+    from paper_2609_24722_amd.cycle import perturb_relax_cycles
+    x, y = W.workload(5, n)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+    log = lambda r: print(json.dumps(r), flush=True)
+    recs = perturb_relax_cycles(xt, yt, cycles, log=log)
+    drift = max(abs(r["energy"] - r["tracked_energy"]) / r["energy"] for r in recs)
+    print(json.dumps({"cycles": cycles, "n": n, "final_energy": recs[-1]["energy"],
+                      "seconds_per_cycle": recs[-1]["wall_s"] / cycles, "max_tracked_drift_rel": drift}),
+          flush=True)
 
 
 def traffic_from_profiles():
@@ -121,6 +212,11 @@ def main():
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-relax", action="store_true")
+    ap.add_argument("--relax-subset", type=int, default=64)
+    ap.add_argument("--cycles", type=int, default=0)
+    ap.add_argument("--cycle-n", type=int, default=40000)
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the all-pairs pass shards by i-range across GPUs "
@@ -131,6 +227,12 @@ def main():
     from paper_2609_24722_amd import FP64, MIXED, ops, workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(dev)
+        return
+    if args.cycles > 0:
+        cycles_mode(dev, args.cycles, args.cycle_n)
+        return
     lib = ops.lib()
     lib.coulomb_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.coulomb_set_kernel_events.restype = None
@@ -150,7 +252,7 @@ def main():
     value = pairs / (step_ms * 1e-3)
     achieved = FLOPS_EF * pairs / (kern_ms * 1e-3) / 1e12
     out = {
-        "metric": "pair-interactions/s (E+F, N=1e5)",
+        "metric": "pair-interactions/s (E+F, N=1e5) & subdomain relax s/cycle at equal E vs FP64",
         "value": value,
         "unit": "pair-interactions/s",
         "n_gpus": 1,
@@ -195,6 +297,8 @@ def main():
         s, k = timed(lambda: ops.energy(xt, yt, MIXED), 5, 1, lib, hip)
         extra["mixed_energy"] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k}
         out["extra"] = extra
+    if not args.no_relax:
+        out["relax"] = relax_comparison(xt, yt, args.relax_subset)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x, y)
     print(json.dumps(out), flush=True)

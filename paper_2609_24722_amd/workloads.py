@@ -119,3 +119,10 @@ def workload(k: int, n: int | None = None):
     if k == 5:
         return warped_lattice(n or 40000, 0.02, 1005)
     raise ValueError(f"unknown workload {k}")
+
+
+def kicked_starts(x, y, idx, kx, ky):
+    """Start positions of kicked candidates: snapshot positions of the packed
+    charge indices plus the kicks (the relaxation projects them into the disk)."""
+    idx = np.asarray(idx)
+    return np.ascontiguousarray(x[idx] + kx), np.ascontiguousarray(y[idx] + ky)
