@@ -13,8 +13,9 @@ namespace cd {
 // Charges per block: one block is one 64-lane wavefront, one charge per lane.
 constexpr int kBlk = 64;
 
-// Pad charges fill the last block.  They sit far outside the disk on the
-// x axis, 1e29 apart: in FP32 every difference involving a pad squares to
+// Pad charges fill the last block (or super-block).  They sit far outside
+// the disk on the x axis, 1e29 apart: in FP32 every difference involving a
+// pad squares to
 // +inf, v_rsq_f32(+inf) = 0 and every term it feeds is exactly zero; in FP64
 // a pad term is below 1e-29 relative to a real one.
 __host__ __device__ inline double pad_x(int64_t k) { return 1e30 + 1e29 * (double)k; }

@@ -5,9 +5,10 @@
 // Pipeline of one call (all on the caller's stream):
 //   1. staging     Morton keys of the FP64 positions, a stable radix sort,
 //                  gather into sorted SoA arrays padded to whole 64-charge
-//                  blocks, per-block centre and bounding box;
-//   2. pair pass   CD_MIXED: symmetric FP32 kernel over block pairs (each
-//                  unordered pair evaluated once, Newton's third law);
+//                  blocks (128-charge super-blocks for CD_MIXED), per-block
+//                  bounding box;
+//   2. pair pass   CD_MIXED: symmetric FP32 kernel over super-block pairs
+//                  (each unordered pair evaluated once, Newton's third law);
 //                  CD_FP64: one-sided FP64 kernel over (i block, j range);
 //   3. reduction   fixed-order sums of the partial results, scattered back
 //                  to the caller's order; energy by a fixed-shape tree.
@@ -16,75 +17,46 @@
 namespace cd {
 
 size_t sort_scratch_elems(int n);
-int sort_pairs(uint32_t* ka, int32_t* va, uint32_t* kb, int32_t* vb, uint32_t* hist, int n,
-               hipStream_t st);
+int morton_order(const double* x, const double* y, int n, uint32_t* ka, uint32_t* kb,
+                 int32_t* va, uint32_t* hist, int32_t* perm, hipStream_t st);
 
 enum Mode { kEnergy = 0, kForces = 1, kHvp = 2 };
 
 // ------------------------------------------------------------------ staging --
-__device__ __forceinline__ uint32_t spread16(uint32_t v) {
-  v &= 0xffffu;
-  v = (v | (v << 8)) & 0x00ff00ffu;
-  v = (v | (v << 4)) & 0x0f0f0f0fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
-  return v;
-}
-
-__global__ void k_morton(const double* __restrict__ x, const double* __restrict__ y, int n,
-                         uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double fx = (x[i] + 1.0) * 32768.0, fy = (y[i] + 1.0) * 32768.0;
-  if (!(fx >= 0.0)) fx = 0.0;
-  if (!(fx <= 65535.0)) fx = 65535.0;
-  if (!(fy >= 0.0)) fy = 0.0;
-  if (!(fy <= 65535.0)) fy = 65535.0;
-  keys[i] = spread16((uint32_t)fx) | (spread16((uint32_t)fy) << 1);
-  idx[i] = i;
-}
-
-// Sorted, padded copies: xs[s] = x[perm[s]] for s < n, pads beyond.
+// Sorted, padded copies (xs[s] = x[perm[s]] for s < n, pads beyond; v only
+// when given) and the bounding box of each block's real charges (+inf..-inf
+// for a block of pads only).  One wave per block.
 __global__ void k_gather(const double* __restrict__ x, const double* __restrict__ y,
                          const double* __restrict__ vx, const double* __restrict__ vy,
-                         const int32_t* __restrict__ perm, int n, int npad,
+                         const int32_t* __restrict__ perm, int n, int nb,
                          double* __restrict__ xs, double* __restrict__ ys,
-                         double* __restrict__ vxs, double* __restrict__ vys) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= npad) return;
-  if (s < n) {
-    int p = perm[s];
-    xs[s] = x[p];
-    ys[s] = y[p];
-    if (vxs && vx) {  // v is gathered only when given (staged HVPs gather it per call)
-      vxs[s] = vx[p];
-      vys[s] = vy[p];
-    }
-  } else {
-    xs[s] = pad_x(s - n);
-    ys[s] = 0.0;
-    if (vxs && vx) {
-      vxs[s] = 0.0;
-      vys[s] = 0.0;
+                         double* __restrict__ vxs, double* __restrict__ vys,
+                         float* __restrict__ box) {
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= nb) return;  // whole waves
+  const int s = b * kBlk + lane;
+  const bool ok = s < n;
+  const bool gv = vxs && vx;  // v is gathered only when given
+  double xv = pad_x(s - n), yv = 0.0, wx = 0.0, wy = 0.0;
+  if (ok) {
+    const int p = perm[s];
+    xv = x[p];
+    yv = y[p];
+    if (gv) {
+      wx = vx[p];
+      wy = vy[p];
     }
   }
-}
-
-// Per block: bounding box of its real charges and the box centre (the
-// reference point of the block's relative coordinates).  One wave per block.
-__global__ void k_blockinfo(const double* __restrict__ xs, const double* __restrict__ ys, int n,
-                            int nb, double* __restrict__ cen, float* __restrict__ box) {
-  int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
-  if (b >= nb) return;
-  int s = b * kBlk + lane;
-  bool ok = s < n;
-  double xv = xs[s], yv = ys[s];
-  double x0 = wave_min(ok ? xv : 1e300), x1 = wave_max(ok ? xv : -1e300);
-  double y0 = wave_min(ok ? yv : 1e300), y1 = wave_max(ok ? yv : -1e300);
+  xs[s] = xv;
+  ys[s] = yv;
+  if (gv) {
+    vxs[s] = wx;
+    vys[s] = wy;
+  }
+  const double x0 = wave_min(ok ? xv : 1e300), x1 = wave_max(ok ? xv : -1e300);
+  const double y0 = wave_min(ok ? yv : 1e300), y1 = wave_max(ok ? yv : -1e300);
   if (lane == 0) {
-    cen[2 * b] = 0.5 * (x0 + x1);
-    cen[2 * b + 1] = 0.5 * (y0 + y1);
     box[4 * b + 0] = (float)x0;
     box[4 * b + 1] = (float)x1;
     box[4 * b + 2] = (float)y0;
@@ -93,44 +65,115 @@ __global__ void k_blockinfo(const double* __restrict__ xs, const double* __restr
 }
 
 // ------------------------------------------------- symmetric FP32 pair pass --
-// Work decomposition.  Blocks I and J = (I + o) mod nb interact for offsets
-// o = 1..floor(nb/2) (for even nb the offset nb/2 only from I < nb/2): every
-// unordered block pair exactly once, the same work for every I.  A workgroup
-// of W waves owns blocks I = gW..gW+W-1 (one per wave, i charges in
-// registers) and the offsets of chunk c: o = cL+1 .. cL+L.  At time step t
-// wave w handles o = cL+1+t, so its j block lands in LDS slot w + t of the
-// workgroup's window of L+W-1 consecutive j blocks; no two waves share a slot
-// in a step, and a barrier separates steps, so the j-side sums accumulate in
-// LDS without atomics and in a fixed order.
+// Work decomposition.  Charges are grouped in super-blocks of NI x 64 (NI =
+// kSymBlocks blocks of 64).  Super-blocks I and J = (I + o) mod ns interact
+// for offsets o = 1..floor(ns/2) (for even ns the offset ns/2 only from
+// I < ns/2): every unordered pair of super-blocks exactly once, the same work
+// for every I.  A workgroup of W waves owns super-blocks I = gW..gW+W-1 (one
+// per wave; each lane holds one charge of each of the NI blocks) and the
+// offsets of chunk c: o = cL+1 .. cL+L.  At time step t wave w handles
+// o = cL+1+t, so its j super-block lands in LDS slot w + t of the
+// workgroup's window of S = L+W-1 consecutive super-blocks; no two waves
+// share a slot in a step and a barrier separates steps, so the j-side sums
+// accumulate in LDS without atomics and in a fixed order.  The pairs inside a
+// super-block (each block's own pairs and the pairs between its blocks) are
+// done by ns more workgroups at the start of the first launch's grid.
 //
-// Inside a block pair each lane owns one i and one j.  Within each 16-lane
-// row the j data rotate by DPP (row_ror:k folded into the subtraction) and
-// the j-side accumulators travel with them (row_ror:1 per step); after 16
+// A step takes the j super-block one 64-charge block at a time, each lane
+// owning one j.  Within each 16-lane row the j data rotate by DPP (row_ror:k
+// folded into the subtractions) and the j-side accumulators travel with them
+// (row_ror:1 per step), one move serving the lane's NI i charges.  After 16
 // steps the rows rotate by a lane permute, four times in all, which covers
-// the 64 x 64 pairs and returns each j accumulator to its own lane.
+// the (NI x 64) x 64 pairs and returns each j accumulator to its own lane.
 //
-// Precision.  Coordinates are taken relative to the centre of block I
-// (FP64 subtraction, then rounded to FP32), so their rounding error scales
-// with the distance from that centre, not with |r|.  For block pairs whose
-// boxes are near each other the low parts fl32(r - c - hi) are kept too and
-// dx = (hi_j - hi_i) + (lo_j - lo_i) is exact to FP32 rounding of dx itself.
-// Per block pair the i and j partials are FP32 sums of 64 terms, folded into
-// FP64 (registers for i, LDS for j).
+// Precision.  Coordinates are taken relative to the centre of the i block's
+// box (FP64 subtraction, then rounded to FP32; the j block is read once for
+// each i block), so their rounding error scales with the distance from that
+// centre, not with |r|.  A j block whose box lies farther from the i block's
+// box than the larger box diagonal gives dx a relative rounding error of at
+// most about 2 ulp; for a nearer one the low parts fl32(r - c - hi) are kept
+// too, and dx = (hi_j - hi_i) + (lo_j - lo_i) is exact to the FP32 rounding
+// of dx itself.  Per block pair the i and j partials are FP32 sums of 64
+// terms, folded into FP64 (registers for i, LDS for j).  The total energy is
+// summed per workgroup, in a fixed order.
+//
+// Batches.  The partial sums of one launch cover the chunks c0..c0+nc-1 and
+// are reduced before the next launch, so their memory is bounded by the batch
+// size Cb, not by the number of chunks C.
+constexpr int NI = kSymBlocks;
+constexpr int SB = NI * kBlk;  // charges per super-block
+
 struct SymArgs {
   const double* xs;
   const double* ys;
   const double* vxs;
   const double* vys;
-  const double* cen;
   const float* box;
-  int nb, npad, W, L, C, G, S;
-  double* ip0;  // i-side partials [C][npad]: fx | hx | e
-  double* ip1;  //                            fy | hy
-  double* ip2;  //                            e (forces mode)
-  double* jp0;  // j-side partials [G*C][S][64]
+  int ns, npad, W, L, C, G, S;
+  int c0, nc, Cb;  // first chunk and chunks of this launch; chunks per batch
+  double* ip0;  // i-side partials [Cb][npad]: fx | hx | e_local
+  double* ip1;  //                             fy | hy
+  double* jp0;  // j-side partials [G*Cb][S][SB]
   double* jp1;
+  double* ep;   // per-workgroup energy partials [Cb][G] (total energy)
+  double* dp0;  // sums of the pairs inside each super-block [npad]
+  double* dp1;
+  double* dep;  // their energy, per super-block [ns]
   double diag_scale;  // weight of the ordered within-block energy sum
 };
+
+// One charge per lane, relative to a reference point: coordinates (hi, lo)
+// and, for Hessian-vector products, v relative to a reference value (hi, lo).
+struct Side {
+  float xh, yh, xl, yl, vx, vy, vxl, vyl;
+};
+
+template <int MODE>
+__device__ __forceinline__ Side load_side(const SymArgs& a, size_t s, double cx, double cy,
+                                          double cvx, double cvy, bool lo) {
+  Side q{};
+  const double rx = a.xs[s] - cx, ry = a.ys[s] - cy;
+  q.xh = (float)rx;
+  q.yh = (float)ry;
+  if (lo) {
+    q.xl = (float)(rx - (double)q.xh);
+    q.yl = (float)(ry - (double)q.yh);
+  }
+  if (MODE == kHvp) {
+    const double wx = a.vxs[s] - cvx, wy = a.vys[s] - cvy;
+    q.vx = (float)wx;
+    q.vy = (float)wy;
+    if (lo) {
+      q.vxl = (float)(wx - (double)q.vx);
+      q.vyl = (float)(wy - (double)q.vy);
+    }
+  }
+  return q;
+}
+
+// The same from FP64 values already loaded (x, y, and v for HVP).
+template <int MODE>
+__device__ __forceinline__ Side make_side(double x, double y, double vx, double vy, double cx,
+                                          double cy, double cvx, double cvy, bool lo) {
+  Side q{};
+  const double rx = x - cx, ry = y - cy;
+  q.xh = (float)rx;
+  q.yh = (float)ry;
+  if (lo) {
+    q.xl = (float)(rx - (double)q.xh);
+    q.yl = (float)(ry - (double)q.yh);
+  }
+  if (MODE == kHvp) {
+    const double wx = vx - cvx, wy = vy - cvy;
+    q.vx = (float)wx;
+    q.vy = (float)wy;
+    if (lo) {
+      q.vxl = (float)(wx - (double)q.vx);
+      q.vyl = (float)(wy - (double)q.vy);
+    }
+  }
+  return q;
+}
 
 template <int MODE, bool LOCAL>
 struct PairOps {
@@ -138,27 +181,26 @@ struct PairOps {
   // i-side accumulators a0,a1,a2; j-side accumulators b0,b1 (already aligned)
   __device__ __forceinline__ static void apply(float dx, float dy, float wx, float wy, float& a0,
                                                float& a1, float& a2, float& b0, float& b1) {
-    float r2 = __builtin_fmaf(dx, dx, dy * dy);
-    float inv = __builtin_amdgcn_rsqf(r2);
+    const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+    const float inv = __builtin_amdgcn_rsqf(r2);
     if (MODE == kEnergy) {
       a2 += inv;
       if (LOCAL) b0 += inv;
     } else if (MODE == kForces) {
       a2 += inv;
-      float i3 = inv * inv * inv;
-      float tx = dx * i3, ty = dy * i3;
-      a0 -= tx;
-      a1 -= ty;
-      b0 += tx;
-      b1 += ty;
+      const float i3 = inv * inv * inv;
+      a0 = __builtin_fmaf(-dx, i3, a0);
+      a1 = __builtin_fmaf(-dy, i3, a1);
+      b0 = __builtin_fmaf(dx, i3, b0);
+      b1 = __builtin_fmaf(dy, i3, b1);
     } else {
-      float i2 = inv * inv;
-      float i3 = i2 * inv;
-      float q = 3.0f * i3 * i2;
-      float dw = __builtin_fmaf(dx, wx, dy * wy);
-      float s = dw * q;
-      float kx = __builtin_fmaf(dx, s, -wx * i3);
-      float ky = __builtin_fmaf(dy, s, -wy * i3);
+      const float i2 = inv * inv;
+      const float i3 = i2 * inv;
+      const float q = 3.0f * i3 * i2;
+      const float dw = __builtin_fmaf(dx, wx, dy * wy);
+      const float s = dw * q;
+      const float kx = __builtin_fmaf(dx, s, -wx * i3);
+      const float ky = __builtin_fmaf(dy, s, -wy * i3);
       a0 -= kx;
       a1 -= ky;
       b0 += kx;
@@ -167,58 +209,74 @@ struct PairOps {
   }
 };
 
+// d = r_j - r_i and w = v_j - v_i for the j data rotated by row_ror:K
+// (K = 0: the lane's own j).
+template <int MODE, bool NEAR, int K>
+__device__ __forceinline__ void diff(const Side& i, const Side& j, float& dx, float& dy,
+                                     float& wx, float& wy) {
+  auto rot = [](float v) {
+    if constexpr (K == 0) return v;
+    else return row_ror<K>(v);
+  };
+  dx = rot(j.xh) - i.xh;
+  dy = rot(j.yh) - i.yh;
+  if (NEAR) {
+    dx += rot(j.xl) - i.xl;
+    dy += rot(j.yl) - i.yl;
+  }
+  wx = 0.f;
+  wy = 0.f;
+  if (MODE == kHvp) {
+    wx = rot(j.vx) - i.vx;
+    wy = rot(j.vy) - i.vy;
+    if (NEAR) {
+      wx += rot(j.vxl) - i.vxl;
+      wy += rot(j.vyl) - i.vyl;
+    }
+  }
+}
+
+// Row rotation by 16 lanes (lane q takes lane q + 16) of the j data.
+template <int MODE, bool NEAR>
+__device__ __forceinline__ void rotate_rows(Side& j, int src) {
+  j.xh = __shfl(j.xh, src, 64);
+  j.yh = __shfl(j.yh, src, 64);
+  if (NEAR) {
+    j.xl = __shfl(j.xl, src, 64);
+    j.yl = __shfl(j.yl, src, 64);
+  }
+  if (MODE == kHvp) {
+    j.vx = __shfl(j.vx, src, 64);
+    j.vy = __shfl(j.vy, src, 64);
+    if (NEAR) {
+      j.vxl = __shfl(j.vxl, src, 64);
+      j.vyl = __shfl(j.vyl, src, 64);
+    }
+  }
+}
+
+// The 64 x 64 pairs of one block pair for the calling lane (one i, one j);
+// ONESIDED: the block with itself, ordered pairs, i side only.
 template <int MODE, bool LOCAL, bool NEAR, bool ONESIDED>
 struct BlockPair {
-  // Processes the 64 x 64 pairs of one block pair for the calling lane.
-  // j data (xjh, yjh, xjl, yjl, vxj, vyj) are modified (rotated).
-  __device__ __forceinline__ static void run(float xih, float yih, float xil, float yil, float vxi,
-                                             float vyi, float vxil, float vyil, float xjh,
-                                             float yjh, float xjl, float yjl, float vxj,
-                                             float vyj, float vxjl, float vyjl, float& a0,
-                                             float& a1, float& a2, float& b0, float& b1,
-                                             int lane) {
+  __device__ __forceinline__ static void run(const Side& i, Side j, float& a0, float& a1,
+                                             float& a2, float& b0, float& b1, int lane) {
     const int src = (lane + 16) & 63;
+    float dx, dy, wx, wy;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      // step 0: own-lane j (skipped for the self pair of a diagonal block)
-      if (!(ONESIDED && p == 0)) {
-        float dx = xjh - xih, dy = yjh - yih;
-        if (NEAR) {
-          dx += xjl - xil;
-          dy += yjl - yil;
-        }
-        float wx = 0.f, wy = 0.f;
-        if (MODE == kHvp) {
-          wx = vxj - vxi;
-          wy = vyj - vyi;
-          if (NEAR) {
-            wx += vxjl - vxil;
-            wy += vyjl - vyil;
-          }
-        }
+      if (!(ONESIDED && p == 0)) {  // the self pair of a diagonal block is skipped
+        diff<MODE, NEAR, 0>(i, j, dx, dy, wx, wy);
         PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1);
       }
-#define CD_SYM_STEP(K)                                                      \
-  {                                                                         \
-    float dx = row_ror<K>(xjh) - xih, dy = row_ror<K>(yjh) - yih;           \
-    if (NEAR) {                                                             \
-      dx += row_ror<K>(xjl) - xil;                                          \
-      dy += row_ror<K>(yjl) - yil;                                          \
-    }                                                                       \
-    float wx = 0.f, wy = 0.f;                                               \
-    if (MODE == kHvp) {                                                     \
-      wx = row_ror<K>(vxj) - vxi;                                           \
-      wy = row_ror<K>(vyj) - vyi;                                           \
-      if (NEAR) {                                                           \
-        wx += row_ror<K>(vxjl) - vxil;                                      \
-        wy += row_ror<K>(vyjl) - vyil;                                      \
-      }                                                                     \
-    }                                                                       \
-    if (!ONESIDED) {                                                        \
-      b0 = row_ror<1>(b0);                                                  \
-      if (MODE != kEnergy) b1 = row_ror<1>(b1);                             \
-    }                                                                       \
-    PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1);        \
+#define CD_SYM_STEP(K)                                                  \
+  {                                                                     \
+    diff<MODE, NEAR, K>(i, j, dx, dy, wx, wy);                          \
+    if (!ONESIDED) {                                                    \
+      b0 = row_ror<1>(b0);                                              \
+      if (MODE != kEnergy) b1 = row_ror<1>(b1);                         \
+    }                                                                   \
+    PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1);    \
   }
       CD_SYM_STEP(1) CD_SYM_STEP(2) CD_SYM_STEP(3) CD_SYM_STEP(4) CD_SYM_STEP(5)
       CD_SYM_STEP(6) CD_SYM_STEP(7) CD_SYM_STEP(8) CD_SYM_STEP(9) CD_SYM_STEP(10)
@@ -230,222 +288,435 @@ struct BlockPair {
         b0 = __shfl(b0, src, 64);
         if (MODE != kEnergy) b1 = __shfl(b1, src, 64);
       }
+      if (p < 3) rotate_rows<MODE, NEAR>(j, src);
+    }
+  }
+};
+
+// The (NI x 64) x 64 pairs of the lane's NI i charges with one j block; j[q]
+// holds the j block relative to the reference point of i block q.  The
+// j-side accumulators are shared.
+template <int MODE, bool LOCAL, bool NEAR>
+struct BlockPairN {
+  __device__ __forceinline__ static void run(const Side (&u)[NI], Side (&j)[NI],
+                                             float (&acc)[NI][3], float& b0, float& b1,
+                                             int lane) {
+    const int src = (lane + 16) & 63;
+    float dx, dy, wx, wy;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        diff<MODE, NEAR, 0>(u[q], j[q], dx, dy, wx, wy);
+        PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1);
+      }
+#define CD_SYM_STEPN(K)                                                                     \
+  {                                                                                         \
+    b0 = row_ror<1>(b0);                                                                    \
+    if (MODE != kEnergy) b1 = row_ror<1>(b1);                                               \
+    _Pragma("unroll") for (int q = 0; q < NI; ++q) {                                        \
+      diff<MODE, NEAR, K>(u[q], j[q], dx, dy, wx, wy);                                      \
+      PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1); \
+    }                                                                                       \
+  }
+      CD_SYM_STEPN(1) CD_SYM_STEPN(2) CD_SYM_STEPN(3) CD_SYM_STEPN(4) CD_SYM_STEPN(5)
+      CD_SYM_STEPN(6) CD_SYM_STEPN(7) CD_SYM_STEPN(8) CD_SYM_STEPN(9) CD_SYM_STEPN(10)
+      CD_SYM_STEPN(11) CD_SYM_STEPN(12) CD_SYM_STEPN(13) CD_SYM_STEPN(14) CD_SYM_STEPN(15)
+#undef CD_SYM_STEPN
+      b0 = row_ror<1>(b0);
+      if (MODE != kEnergy) b1 = row_ror<1>(b1);
+      b0 = __shfl(b0, src, 64);
+      if (MODE != kEnergy) b1 = __shfl(b1, src, 64);
       if (p < 3) {
-        xjh = __shfl(xjh, src, 64);
-        yjh = __shfl(yjh, src, 64);
-        if (NEAR) {
-          xjl = __shfl(xjl, src, 64);
-          yjl = __shfl(yjl, src, 64);
-        }
-        if (MODE == kHvp) {
-          vxj = __shfl(vxj, src, 64);
-          vyj = __shfl(vyj, src, 64);
-          if (NEAR) {
-            vxjl = __shfl(vxjl, src, 64);
-            vyjl = __shfl(vyjl, src, 64);
-          }
-        }
+#pragma unroll
+        for (int q = 0; q < NI; ++q) rotate_rows<MODE, NEAR>(j[q], src);
       }
     }
   }
 };
 
+// Centre of a box side in FP64; 0 for the empty side of a block of pads.
+__device__ __forceinline__ double centre(float lo, float hi) {
+  return lo <= hi ? 0.5 * ((double)lo + (double)hi) : 0.0;
+}
+
 __device__ __forceinline__ bool boxes_near(const float* box, int I, int J) {
-  // gap between the two boxes below twice the larger box diagonal
+  // gap between the two boxes below the larger box diagonal
   float ix0 = box[4 * I], ix1 = box[4 * I + 1], iy0 = box[4 * I + 2], iy1 = box[4 * I + 3];
   float jx0 = box[4 * J], jx1 = box[4 * J + 1], jy0 = box[4 * J + 2], jy1 = box[4 * J + 3];
   float gx = fmaxf(0.f, fmaxf(jx0 - ix1, ix0 - jx1));
   float gy = fmaxf(0.f, fmaxf(jy0 - iy1, iy0 - jy1));
   float di = (ix1 - ix0) * (ix1 - ix0) + (iy1 - iy0) * (iy1 - iy0);
   float dj = (jx1 - jx0) * (jx1 - jx0) + (jy1 - jy0) * (jy1 - jy0);
-  return gx * gx + gy * gy < 4.f * fmaxf(di, dj);
+  return gx * gx + gy * gy < fmaxf(di, dj);
 }
+
+// acc[k] += (v0, v1, v2) for the k selected by a wave-uniform index.
+__device__ __forceinline__ void add_at(double (&U)[NI][3], int k, double v0, double v1,
+                                       double v2) {
+#pragma unroll
+  for (int q = 0; q < NI; ++q)
+    if (q == k) {
+      U[q][0] += v0;
+      U[q][1] += v1;
+      U[q][2] += v2;
+    }
+}
+
+// The pairs inside super-block I, by one workgroup: block pair p = (q, r),
+// q <= r, of its NI blocks (q = r: the block's own ordered pairs, i side
+// only) goes to wave p mod W.  The sums of each charge are combined in LDS in
+// a fixed order and written to dp (forces, HVP: two components; local
+// energies: one); the energy goes to dep[I].
+constexpr int kDiagPairs = NI * (NI + 1) / 2;
+
+constexpr size_t kDiagLds = sizeof(float) * kDiagPairs * 2 * 3 * kBlk;
 
 template <int MODE, bool LOCAL>
-__global__ __launch_bounds__(1024) void k_sym(SymArgs a) {
-  extern __shared__ double lds[];  // [S][NJ][64]
-  constexpr int NJ = (MODE == kEnergy) ? 1 : 2;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x / a.C, c = blockIdx.x % a.C;
-  const int I = g * a.W + w;
-  const bool wave_ok = I < a.nb;
-  const int hmax = a.nb / 2;
-  for (int e = threadIdx.x; e < a.S * NJ * kBlk; e += blockDim.x) lds[e] = 0.0;
-
-  double A0 = 0.0, A1 = 0.0, A2 = 0.0;
-  float xih = 0.f, yih = 0.f, xil = 0.f, yil = 0.f, vxi = 0.f, vyi = 0.f, vxil = 0.f, vyil = 0.f;
-  double cx = 0.0, cy = 0.0, cvx = 0.0, cvy = 0.0;
-  if (wave_ok) {
-    const int si = I * kBlk + lane;
-    cx = a.cen[2 * I];
-    cy = a.cen[2 * I + 1];
-    double rx = a.xs[si] - cx, ry = a.ys[si] - cy;
-    xih = (float)rx;
-    yih = (float)ry;
-    xil = (float)(rx - (double)xih);
-    yil = (float)(ry - (double)yih);
-    if (MODE == kHvp) {
-      // v is also taken relative to a reference value of block I (its first
-      // charge), so that differences of a smooth v keep their precision
-      cvx = a.vxs[(size_t)I * kBlk];
-      cvy = a.vys[(size_t)I * kBlk];
-      double wx = a.vxs[si] - cvx, wy = a.vys[si] - cvy;
-      vxi = (float)wx;
-      vyi = (float)wy;
-      vxil = (float)(wx - (double)vxi);
-      vyil = (float)(wy - (double)vyi);
+__device__ __forceinline__ void sym_diag(const SymArgs& a, int I, int w, int lane,
+                                         float (*part)[2][3][kBlk]) {
+  // part[pair][i side | j side][component][lane], in the dynamic LDS
+  __shared__ double red[16];
+  double rvx = 0.0, rvy = 0.0;
+  if (MODE == kHvp) {
+    rvx = a.vxs[(size_t)I * SB];
+    rvy = a.vys[(size_t)I * SB];
+  }
+#pragma unroll 1
+  for (int p = w; p < kDiagPairs; p += a.W) {
+    int q = 0, r = p;  // pair p in the order (0,0), (0,1), .., (0,NI-1), (1,1), ..
+    while (r >= NI - q) {
+      r -= NI - q;
+      ++q;
     }
-    if (c == 0) {
-      // diagonal block: ordered pairs within the block, i side only
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f;
-      BlockPair<MODE, false, true, true>::run(xih, yih, xil, yil, vxi, vyi, vxil, vyil, xih, yih,
-                                              xil, yil, vxi, vyi, vxil, vyil, a0, a1, a2, b0, b1,
-                                              lane);
-      A0 += (double)a0;
-      A1 += (double)a1;
-      A2 += a.diag_scale * (double)a2;
+    r += q;
+    const float* bq = a.box + 4 * ((size_t)NI * I + q);
+    const double ccx = centre(bq[0], bq[1]), ccy = centre(bq[2], bq[3]);
+    const Side sq =
+        load_side<MODE>(a, (size_t)I * SB + q * kBlk + lane, ccx, ccy, rvx, rvy, true);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f;
+    if (q == r) {
+      BlockPair<MODE, false, true, true>::run(sq, sq, a0, a1, a2, b0, b1, lane);
+      b0 = b1 = 0.f;
+    } else {
+      const Side sr =
+          load_side<MODE>(a, (size_t)I * SB + r * kBlk + lane, ccx, ccy, rvx, rvy, true);
+      BlockPair<MODE, LOCAL, true, false>::run(sq, sr, a0, a1, a2, b0, b1, lane);
     }
+    const float dscale = q == r ? (float)a.diag_scale : 1.f;  // 0.5 or 1: exact in FP32
+    part[p][0][0][lane] = a0;
+    part[p][0][1][lane] = a1;
+    part[p][0][2][lane] = a2 * dscale;
+    // j side: forces/HVP components, or (local energies) the energy
+    part[p][1][0][lane] = MODE == kEnergy ? 0.f : b0;
+    part[p][1][1][lane] = MODE == kEnergy ? 0.f : b1;
+    part[p][1][2][lane] = (MODE == kEnergy && LOCAL) ? b0 : 0.f;
   }
   __syncthreads();
-
-  for (int t = 0; t < a.L; ++t) {
-    const int o = c * a.L + 1 + t;
-    const bool ok = wave_ok && o <= hmax && (2 * o < a.nb || I < hmax);
-    if (ok) {
-      int J = I + o;
-      if (J >= a.nb) J -= a.nb;
-      const int sj = J * kBlk + lane;
-      double rx = a.xs[sj] - cx, ry = a.ys[sj] - cy;
-      float xjh = (float)rx, yjh = (float)ry;
-      float vxj = 0.f, vyj = 0.f;
-      double wx = 0.0, wy = 0.0;
-      if (MODE == kHvp) {
-        wx = a.vxs[sj] - cvx;
-        wy = a.vys[sj] - cvy;
-        vxj = (float)wx;
-        vyj = (float)wy;
-      }
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f;
-      if (boxes_near(a.box, I, J)) {
-        float xjl = (float)(rx - (double)xjh), yjl = (float)(ry - (double)yjh);
-        float vxjl = 0.f, vyjl = 0.f;
-        if (MODE == kHvp) {
-          vxjl = (float)(wx - (double)vxj);
-          vyjl = (float)(wy - (double)vyj);
+  double es = 0.0;  // this thread's share of the energy
+  for (int t = threadIdx.x; t < SB; t += blockDim.x) {
+    const int k = t / kBlk, l = t % kBlk;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    int p = 0;
+    for (int pq = 0; pq < NI; ++pq)
+      for (int pr = pq; pr < NI; ++pr, ++p) {
+        if (pq == k) {
+          v0 += (double)part[p][0][0][l];
+          v1 += (double)part[p][0][1][l];
+          v2 += (double)part[p][0][2][l];
         }
-        BlockPair<MODE, LOCAL, true, false>::run(xih, yih, xil, yil, vxi, vyi, vxil, vyil, xjh,
-                                                 yjh, xjl, yjl, vxj, vyj, vxjl, vyjl, a0, a1, a2,
-                                                 b0, b1, lane);
-      } else {
-        BlockPair<MODE, LOCAL, false, false>::run(xih, yih, xil, yil, vxi, vyi, vxil, vyil, xjh,
-                                                  yjh, 0.f, 0.f, vxj, vyj, 0.f, 0.f, a0, a1, a2,
-                                                  b0, b1, lane);
+        if (pr == k && pq != pr) {
+          v0 += (double)part[p][1][0][l];
+          v1 += (double)part[p][1][1][l];
+          v2 += (double)part[p][1][2][l];
+        }
       }
-      A0 += (double)a0;
-      A1 += (double)a1;
-      A2 += (double)a2;
-      if (MODE != kEnergy || LOCAL) {
-        double* sl = lds + (size_t)(w + t) * NJ * kBlk;
-        sl[lane] += (double)b0;
-        if (NJ > 1) sl[kBlk + lane] += (double)b1;
-      }
+    const size_t s = (size_t)I * SB + t;
+    if (MODE == kEnergy && LOCAL) {
+      a.dp0[s] = v2;
+    } else if (MODE != kEnergy) {
+      a.dp0[s] = v0;
+      a.dp1[s] = v1;
     }
+    es += v2;
+  }
+  if (MODE != kHvp && !LOCAL) {
+    const double ws = wave_sum(es);
+    if (lane == 0) red[w] = ws;
     __syncthreads();
-  }
-
-  if (wave_ok) {
-    const size_t si = (size_t)c * a.npad + (size_t)I * kBlk + lane;
-    if (MODE == kEnergy) {
-      a.ip0[si] = A2;
-    } else {
-      a.ip0[si] = A0;
-      a.ip1[si] = A1;
-      if (MODE == kForces) a.ip2[si] = A2;
-    }
-  }
-  if (MODE != kEnergy || LOCAL) {
-    const size_t base = (size_t)blockIdx.x * a.S * kBlk;
-    for (int e = threadIdx.x; e < a.S * kBlk; e += blockDim.x) {
-      const int slot = e / kBlk, l = e % kBlk;
-      a.jp0[base + e] = lds[(size_t)slot * NJ * kBlk + l];
-      if (NJ > 1) a.jp1[base + e] = lds[(size_t)slot * NJ * kBlk + kBlk + l];
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+      a.dep[I] = t;
     }
   }
 }
 
-// Sum of the partials for sorted index s, in a fixed order: i-side chunks,
-// then for each chunk the workgroups whose j window contains block B.
+// Occupancy: the energy and force variants are held to the register budget
+// of kSymWavesPerSimd waves per SIMD.
+template <int MODE, bool LOCAL>
+__global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(
+    MODE == kHvp ? 1 : kSymWavesPerSimd))) void k_sym(SymArgs a) {
+  extern __shared__ double lds[];  // [S][NJ][SB]
+  constexpr int NJ = (MODE == kEnergy) ? 1 : 2;
+  constexpr bool JSIDE = MODE != kEnergy || LOCAL;  // j-side sums are kept
+  __shared__ double ered[16];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  // chunk-major dispatch: chunk 0 (which also does the super-diagonals)
+  // starts first, the last chunk (possibly short) ends the grid
+  int bid = blockIdx.x;
+  if (a.c0 == 0) {
+    // first launch: workgroups 0..ns-1 do the pairs inside super-block bid,
+    // dispatched first so that they overlap the chunk grid
+    if (bid < a.ns) {
+      sym_diag<MODE, LOCAL>(a, bid, w, lane, reinterpret_cast<float(*)[2][3][kBlk]>(lds));
+      return;
+    }
+    bid -= a.ns;
+  }
+  const int cl = bid / a.G, g = bid % a.G;
+  const int c = a.c0 + cl;
+  const int task = g * a.Cb + cl;  // index of this workgroup's partials in the batch
+  const int I = g * a.W + w;
+  const bool wave_ok = I < a.ns;
+  const int hmax = a.ns / 2;
+  if (JSIDE)
+    for (int e = threadIdx.x; e < a.S * NJ * SB; e += blockDim.x) lds[e] = 0.0;
+
+  double U[NI][3];
+  Side u[NI];
+  double cx[NI], cy[NI];
+  double rvx = 0.0, rvy = 0.0;
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    U[q][0] = U[q][1] = U[q][2] = 0.0;
+    cx[q] = cy[q] = 0.0;
+    u[q] = Side{};
+  }
+  if (wave_ok) {
+    // reference points: the centres of the blocks' boxes (a block of pads
+    // only has the empty box +inf..-inf and the centre 0)
+    const float* bx = a.box + 4 * NI * (size_t)I;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      cx[q] = centre(bx[4 * q], bx[4 * q + 1]);
+      cy[q] = centre(bx[4 * q + 2], bx[4 * q + 3]);
+    }
+    if (MODE == kHvp) {
+      // v relative to the super-block's first charge, so that differences of
+      // a smooth v keep their precision
+      rvx = a.vxs[(size_t)I * SB];
+      rvy = a.vys[(size_t)I * SB];
+    }
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+      u[q] = load_side<MODE>(a, (size_t)I * SB + q * kBlk + lane, cx[q], cy[q], rvx, rvy, true);
+  }
+  if (JSIDE) __syncthreads();
+
+  // Passes e = t * NI + h: step t, j block h of the step's super-block.  The
+  // j charges of the next pass are loaded while the current one computes.
+  auto pass_block = [&](int e) -> int {  // j block of pass e, -1 if none
+    const int o = c * a.L + 1 + e / NI;
+    if (!(wave_ok && o <= hmax && (2 * o < a.ns || I < hmax))) return -1;
+    int J = I + o;
+    if (J >= a.ns) J -= a.ns;
+    return NI * J + e % NI;
+  };
+  const int npass = a.L * NI;
+  double nx = 0.0, ny = 0.0, nvx = 0.0, nvy = 0.0;
+  int jbn = pass_block(0);
+  if (jbn >= 0) {
+    const size_t sj = (size_t)jbn * kBlk + lane;
+    nx = a.xs[sj];
+    ny = a.ys[sj];
+    if (MODE == kHvp) {
+      nvx = a.vxs[sj];
+      nvy = a.vys[sj];
+    }
+  }
+#pragma unroll 1
+  for (int e = 0; e < npass; ++e) {
+    const int jb = jbn;
+    const double jx = nx, jy = ny, jvx = nvx, jvy = nvy;
+    jbn = e + 1 < npass ? pass_block(e + 1) : -1;
+    if (jbn >= 0) {
+      const size_t sj = (size_t)jbn * kBlk + lane;
+      nx = a.xs[sj];
+      ny = a.ys[sj];
+      if (MODE == kHvp) {
+        nvx = a.vxs[sj];
+        nvy = a.vys[sj];
+      }
+    }
+    if (jb >= 0) {
+      bool near = false;
+#pragma unroll
+      for (int q = 0; q < NI; ++q) near = near || boxes_near(a.box, NI * I + q, jb);
+      Side j[NI];
+#pragma unroll
+      for (int q = 0; q < NI; ++q)
+        j[q] = make_side<MODE>(jx, jy, jvx, jvy, cx[q], cy[q], rvx, rvy, near);
+      float acc[NI][3];
+#pragma unroll
+      for (int q = 0; q < NI; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.f;
+      float b0 = 0.f, b1 = 0.f;
+      if (near)
+        BlockPairN<MODE, LOCAL, true>::run(u, j, acc, b0, b1, lane);
+      else
+        BlockPairN<MODE, LOCAL, false>::run(u, j, acc, b0, b1, lane);
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        U[q][0] += (double)acc[q][0];
+        U[q][1] += (double)acc[q][1];
+        U[q][2] += (double)acc[q][2];
+      }
+      if (JSIDE) {
+        double* sl = lds + (size_t)(w + e / NI) * NJ * SB + (e % NI) * kBlk;
+        sl[lane] += (double)b0;
+        if (NJ > 1) sl[SB + lane] += (double)b1;
+      }
+    }
+    if (JSIDE && e % NI == NI - 1) __syncthreads();
+  }
+
+  const size_t si = (size_t)cl * a.npad + (size_t)I * SB + lane;
+  if (MODE == kEnergy && LOCAL) {
+    if (wave_ok) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) a.ip0[si + q * kBlk] = U[q][2];
+    }
+  } else {
+    if (MODE != kEnergy && wave_ok) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        a.ip0[si + q * kBlk] = U[q][0];
+        a.ip1[si + q * kBlk] = U[q][1];
+      }
+    }
+    if (MODE != kHvp) {
+      double es = 0.0;
+#pragma unroll
+      for (int q = 0; q < NI; ++q) es += U[q][2];
+      const double e = wave_sum(es);
+      if (lane == 0) ered[w] = e;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double tt = 0.0;
+        for (int q = 0; q < a.W; ++q) tt += ered[q];
+        a.ep[(size_t)cl * a.G + g] = tt;  // the batch's sums are contiguous
+      }
+    }
+  }
+  if (JSIDE) {
+    const size_t base = (size_t)task * a.S * SB;
+    for (int e = threadIdx.x; e < a.S * SB; e += blockDim.x) {
+      const int slot = e / SB, l = e % SB;
+      a.jp0[base + e] = lds[(size_t)slot * NJ * SB + l];
+      if (NJ > 1) a.jp1[base + e] = lds[(size_t)slot * NJ * SB + SB + l];
+    }
+  }
+}
+
+// Sum of one batch's partials for sorted index s, in a fixed order: the
+// i-side chunks, then for each chunk the workgroups whose j window contains
+// super-block B.  One workgroup of 2 x SB threads per super-block: the first
+// SB threads take the first component of its charges, the others the second.
+// The list of j partial slots (the same for all charges of B) is built first
+// in LDS, so the loads can be issued in groups.
 struct SymReduceArgs {
   const double* ip0;
   const double* ip1;
-  const double* ip2;
   const double* jp0;
   const double* jp1;
+  const double* dp0;  // sums of the pairs inside the super-blocks (added by the first batch)
+  const double* dp1;
   const int32_t* perm;
-  int n, nb, npad, W, L, C, G, S;
-  double* out0;  // fx | hx | e_local (caller order), may be null
-  double* out1;  // fy | hy
-  double* eblk;  // per-workgroup energy partial
+  int n, ns, npad, W, L, C, G, S;
+  int c0, nc, Cb, mj;  // batch: first chunk, chunks, stride; list entries per chunk
+  int first, last;     // first batch writes the outputs, later ones add to them
+  double* out0;        // fx | hx | e_local (caller order)
+  double* out1;        // fy | hy
+  double* eblk;        // per-super-block sum of e_local (last batch)
 };
 
-template <int MODE, bool LOCAL>
-__global__ __launch_bounds__(256) void k_sym_reduce(SymReduceArgs a) {
-  __shared__ double red[4];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  double v0 = 0.0, v1 = 0.0, ve = 0.0;
-  if (s < a.n) {
-    const int B = s / kBlk, l = s % kBlk;
-    for (int c = 0; c < a.C; ++c) {
-      const size_t k = (size_t)c * a.npad + s;
-      if (MODE == kEnergy) {
-        ve += a.ip0[k];
-      } else {
-        v0 += a.ip0[k];
-        v1 += a.ip1[k];
-        if (MODE == kForces) ve += a.ip2[k];
-      }
+template <int MODE>
+__global__ __launch_bounds__(2 * SB) void k_sym_reduce(SymReduceArgs a) {
+  extern __shared__ int32_t lst[];  // [nc][mj]: j partial slots, -1 for none
+  __shared__ double red[SB / 64];
+  const int B = blockIdx.x;
+  for (int cl = threadIdx.x; cl < a.nc; cl += blockDim.x) {
+    // workgroup (g, c) holds super-block J in slot (J - gW - cL - 1) mod ns
+    // when that is < S; with u = (B - cL - 1) mod ns the bases gW that
+    // qualify are u - slot + k*ns (k = 0, 1, 2), three disjoint ranges
+    const int c = a.c0 + cl;
+    int32_t* out = lst + cl * a.mj;
+    int e = 0;
+    int u = (B - c * a.L - 1) % a.ns;
+    if (u < 0) u += a.ns;
+    for (int k = 0; k < 3; ++k) {
+      const int hi = u + k * a.ns, lo = hi - a.S + 1;
+      const int g0 = lo <= 0 ? 0 : (lo + a.W - 1) / a.W;
+      int g1 = hi / a.W;
+      if (g1 > a.G - 1) g1 = a.G - 1;
+      for (int g = g0; g <= g1 && e < a.mj; ++g) out[e++] = (g * a.Cb + cl) * a.S + (hi - g * a.W);
     }
-    if (MODE != kEnergy || LOCAL) {
-      for (int c = 0; c < a.C; ++c) {
-        // workgroup (g, c) holds block J in slot (J - gW - cL - 1) mod nb when
-        // that is < S; with u = (B - cL - 1) mod nb the bases gW that qualify
-        // are u - slot + k*nb (k = 0, 1, 2), three disjoint ranges
-        int u = (B - c * a.L - 1) % a.nb;
-        if (u < 0) u += a.nb;
-        for (int k = 0; k < 3; ++k) {
-          const int hi = u + k * a.nb, lo = hi - a.S + 1;
-          int g0 = lo <= 0 ? 0 : (lo + a.W - 1) / a.W;
-          int g1 = hi / a.W;
-          if (g1 > a.G - 1) g1 = a.G - 1;
-          for (int g = g0; g <= g1; ++g) {
-            const int slot = hi - g * a.W;
-            const size_t q = ((size_t)(g * a.C + c) * a.S + slot) * kBlk + l;
-            if (MODE == kEnergy) {
-              ve += a.jp0[q];
-            } else {
-              v0 += a.jp0[q];
-              v1 += a.jp1[q];
-            }
-          }
-        }
-      }
+    for (; e < a.mj; ++e) out[e] = -1;
+  }
+  __syncthreads();
+  const int comp = threadIdx.x / SB, l = threadIdx.x % SB;
+  const bool act = MODE != kEnergy || comp == 0;
+  const int s = B * SB + l;
+  const double* ip = comp ? a.ip1 : a.ip0;
+  const double* jp = comp ? a.jp1 : a.jp0;
+  double v = 0.0;
+  if (act) {
+    if (a.first) v = (comp ? a.dp1 : a.dp0)[s];
+    int k = 0;
+    for (; k + 8 <= a.nc; k += 8) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = ip[(size_t)(k + q) * a.npad + s];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += t[q];
     }
-    const int p = a.perm[s];
-    if (MODE == kEnergy) {
-      if (LOCAL) {
-        ve *= 0.5;
-        if (a.out0) a.out0[p] = ve;
+    for (; k < a.nc; ++k) v += ip[(size_t)k * a.npad + s];
+    const int m = a.nc * a.mj;
+    k = 0;
+    for (; k + 8 <= m; k += 8) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = lst[k + q];
+        t[q] = j >= 0 ? jp[(size_t)j * SB + l] : 0.0;
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += t[q];
+    }
+    for (; k < m; ++k) {
+      const int j = lst[k];
+      if (j >= 0) v += jp[(size_t)j * SB + l];
+    }
+    if (s < a.n) {
+      double* out = comp ? a.out1 : a.out0;
+      const int p = a.perm[s];
+      if (!a.first) v = out[p] + v;
+      if (MODE == kEnergy && a.last) v *= 0.5;
+      out[p] = v;
     } else {
-      a.out0[p] = v0;
-      a.out1[p] = v1;
+      v = 0.0;
     }
   }
-  if (MODE != kHvp) {
-    double ws = wave_sum(ve);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  if (MODE == kEnergy && a.last) {
+    const double ws = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < SB) red[threadIdx.x >> 6] = ws;
     __syncthreads();
-    if (threadIdx.x == 0) a.eblk[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < SB / 64; ++q) t += red[q];
+      a.eblk[B] = t;
+    }
   }
 }
 
@@ -572,17 +843,34 @@ __global__ __launch_bounds__(256) void k_one64_reduce(OneReduceArgs a) {
   }
 }
 
-// Final energy: one workgroup sums the per-workgroup partials in a fixed
-// order (strided per-thread sums, then a fixed tree).
-__global__ __launch_bounds__(256) void k_sum_blocks(const double* __restrict__ eblk, int m,
-                                                    double* __restrict__ out) {
-  __shared__ double red[4];
+// Final energy: one workgroup of 1024 threads sums the m partials in a fixed
+// order (per thread the elements t, t + 1024, ... in order, loads issued in
+// groups of 8; then the waves' sums in order).
+__global__ __launch_bounds__(1024) void k_sum_blocks(const double* __restrict__ eblk, int m,
+                                                     double* __restrict__ out) {
+  __shared__ double red[16];
   double v = 0.0;
-  for (int k = threadIdx.x; k < m; k += blockDim.x) v += eblk[k];
+  int k = threadIdx.x;
+  for (; k + 7 * 1024 < m; k += 8 * 1024) {
+    double t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[q] = eblk[k + q * 1024];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += t[q];
+  }
+  for (; k < m; k += 1024) v += eblk[k];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q];
+    *out = t;
+  }
+}
+
+static void sum_blocks(const double* part, int m, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, st, part, m, out);
 }
 
 // ------------------------------------------------------------- validation --
@@ -613,13 +901,26 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
   P.npad = P.nb * kBlk;
   const int mode = op == CD_OP_ENERGY ? kEnergy : op == CD_OP_FORCES ? kForces : kHvp;
   if (precision == CD_MIXED && op != CD_OP_VALIDATE) {
-    P.W = P.nb < 16 ? P.nb : 16;
-    int l = P.nb + 1 - P.W;
-    P.L = l < 1 ? 1 : (l > 32 ? 32 : l);
-    const int hmax = P.nb / 2;
+    P.ns = (n + SB - 1) / SB;
+    P.nb = NI * P.ns;
+    P.npad = P.nb * kBlk;
+    // W waves per workgroup, L offsets per chunk; S = L + W - 1 <= ns keeps
+    // the j window from wrapping onto itself
+    P.W = P.ns < kSymWaves ? P.ns : kSymWaves;
+    const int l = P.ns + 1 - P.W;
+    P.L = l < 1 ? 1 : (l > kSymChunk ? kSymChunk : l);
+    const int hmax = P.ns / 2;
     P.C = hmax > 0 ? (hmax + P.L - 1) / P.L : 1;
-    P.G = (P.nb + P.W - 1) / P.W;
+    P.G = (P.ns + P.W - 1) / P.W;
     P.S = P.L + P.W - 1;
+    P.mj = (P.S + P.W - 1) / P.W + 1;  // j partial slots of one super-block per chunk
+    // chunks per batch: partial sums of at most kSymBatchBytes (at least one chunk)
+    const size_t per = ((size_t)P.npad + (size_t)P.G * P.S * SB) * sizeof(double) *
+                       (mode == kEnergy ? 1 : 2);
+    size_t cb = kSymBatchBytes / per;
+    if (cb < 1) cb = 1;
+    if (cb > (size_t)kSymBatchMax) cb = kSymBatchMax;
+    P.Cb = cb < (size_t)P.C ? (int)cb : P.C;
   } else {
     // enough waves to fill 256 CUs several times over
     int sp = (16384 + P.nb - 1) / P.nb;
@@ -633,7 +934,7 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
   cv.base = base;
   P.keys = cv.take<uint32_t>(n);
   P.keys2 = cv.take<uint32_t>(n);
-  P.perm = cv.take<int32_t>(P.npad);
+  P.perm = cv.take<int32_t>(n);
   P.perm2 = cv.take<int32_t>(n);
   P.hist = cv.take<uint32_t>(sort_scratch_elems(n));
   P.xs = cv.take<double>(P.npad);
@@ -642,19 +943,29 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
     P.vxs = cv.take<double>(P.npad);
     P.vys = cv.take<double>(P.npad);
   }
-  P.cen = cv.take<double>(2 * (size_t)P.nb);
   P.box = cv.take<float>(4 * (size_t)P.nb);
   if (op != CD_OP_VALIDATE) {
-    const size_t q = (precision == CD_MIXED ? (size_t)P.C : (size_t)P.splits) * P.npad;
-    P.q0 = cv.take<double>(q);
-    if (mode != kEnergy) P.q1 = cv.take<double>(q);
-    if (mode == kForces) P.q2 = cv.take<double>(q);
     if (precision == CD_MIXED) {
-      const size_t jq = (size_t)P.G * P.C * P.S * kBlk;
+      const size_t q = (size_t)P.Cb * P.npad;
+      P.q0 = cv.take<double>(q);
+      if (mode != kEnergy) P.q1 = cv.take<double>(q);
+      const size_t jq = (size_t)P.G * P.Cb * P.S * SB;
       P.j0 = cv.take<double>(jq);
       if (mode != kEnergy) P.j1 = cv.take<double>(jq);
+      P.dp0 = cv.take<double>(P.npad);
+      if (mode != kEnergy) P.dp1 = cv.take<double>(P.npad);
+      if (mode != kHvp) {
+        P.ep = cv.take<double>((size_t)P.ns + (size_t)P.G * P.Cb);  // diagonal, then batch
+        P.eb = cv.take<double>((P.C + P.Cb - 1) / P.Cb);
+      }
+      P.eblk = cv.take<double>(P.ns);
+    } else {
+      const size_t q = (size_t)P.splits * P.npad;
+      P.q0 = cv.take<double>(q);
+      if (mode != kEnergy) P.q1 = cv.take<double>(q);
+      if (mode == kForces) P.q2 = cv.take<double>(q);
+      P.eblk = cv.take<double>(P.nred);
     }
-    P.eblk = cv.take<double>(P.nred);
   }
   P.total = cv.off + 256;
   return true;
@@ -663,14 +974,10 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
 int stage(const Plan& P, const double* x, const double* y, const double* vx,
                  const double* vy, hipStream_t st) {
   const int n = P.n;
-  hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, st, x, y, n, P.keys,
-                     P.perm);
-  int rc = sort_pairs(P.keys, P.perm, P.keys2, P.perm2, P.hist, n, st);
+  int rc = morton_order(x, y, n, P.keys, P.keys2, P.perm2, P.hist, P.perm, st);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_gather, dim3((P.npad + 255) / 256), dim3(256), 0, st, x, y, vx, vy,
-                     P.perm, n, P.npad, P.xs, P.ys, P.vxs, P.vys);
-  hipLaunchKernelGGL(k_blockinfo, dim3((P.nb + 3) / 4), dim3(256), 0, st, P.xs, P.ys, n, P.nb,
-                     P.cen, P.box);
+  hipLaunchKernelGGL(k_gather, dim3((P.nb + 3) / 4), dim3(256), 0, st, x, y, vx, vy, P.perm, n,
+                     P.nb, P.xs, P.ys, P.vxs, P.vys, P.box);
   return hip_status(hipGetLastError());
 }
 
@@ -682,52 +989,87 @@ static void mark(hipEvent_t ev, hipStream_t st) {
   if (ev) (void)hipEventRecord(ev, st);
 }
 
+// Symmetric pass in batches of chunks, each followed by its reduction, and
+// (forces, energy) the total energy.
 template <int MODE, bool LOCAL>
-static void run_sym(const Plan& P, hipStream_t st, double* out0, double* out1) {
+static void run_sym(const Plan& P, hipStream_t st, double* out0, double* out1, double* e_total) {
   SymArgs a;
   a.xs = P.xs;
   a.ys = P.ys;
   a.vxs = P.vxs;
   a.vys = P.vys;
-  a.cen = P.cen;
   a.box = P.box;
-  a.nb = P.nb;
+  a.ns = P.ns;
   a.npad = P.npad;
   a.W = P.W;
   a.L = P.L;
   a.C = P.C;
   a.G = P.G;
   a.S = P.S;
+  a.Cb = P.Cb;
   a.ip0 = P.q0;
   a.ip1 = P.q1;
-  a.ip2 = P.q2;
   a.jp0 = P.j0;
   a.jp1 = P.j1;
+  a.ep = P.ep ? P.ep + P.ns : nullptr;
   a.diag_scale = (MODE == kEnergy && LOCAL) ? 1.0 : 0.5;
+  constexpr bool JSIDE = MODE != kEnergy || LOCAL;
   constexpr int NJ = (MODE == kEnergy) ? 1 : 2;
-  const size_t lds = (size_t)P.S * NJ * kBlk * sizeof(double);
-  mark(g_ev_start, st);
-  hipLaunchKernelGGL((k_sym<MODE, LOCAL>), dim3(P.G * P.C), dim3(64 * P.W), lds, st, a);
-  mark(g_ev_stop, st);
+  size_t lds = JSIDE ? (size_t)P.S * NJ * SB * sizeof(double) : 0;
+  if (lds < kDiagLds) lds = kDiagLds;
   SymReduceArgs r;
   r.ip0 = P.q0;
   r.ip1 = P.q1;
-  r.ip2 = P.q2;
   r.jp0 = P.j0;
   r.jp1 = P.j1;
+  r.dp0 = P.dp0;
+  r.dp1 = P.dp1;
   r.perm = P.perm;
   r.n = P.n;
-  r.nb = P.nb;
+  r.ns = P.ns;
   r.npad = P.npad;
   r.W = P.W;
   r.L = P.L;
   r.C = P.C;
   r.G = P.G;
   r.S = P.S;
+  r.Cb = P.Cb;
+  r.mj = P.mj;
   r.out0 = out0;
   r.out1 = out1;
   r.eblk = P.eblk;
-  hipLaunchKernelGGL((k_sym_reduce<MODE, LOCAL>), dim3(P.nred), dim3(256), 0, st, r);
+  const int nbatch = (P.C + P.Cb - 1) / P.Cb;
+  constexpr bool ESUM = MODE != kHvp && !LOCAL;  // total energy from the per-workgroup sums
+  a.dp0 = P.dp0;
+  a.dp1 = P.dp1;
+  a.dep = P.ep;
+  mark(g_ev_start, st);
+  for (int c0 = 0, b = 0; c0 < P.C; c0 += P.Cb, ++b) {
+    const int nc = P.C - c0 < P.Cb ? P.C - c0 : P.Cb;
+    a.c0 = c0;
+    a.nc = nc;
+    const int grid = P.G * nc + (c0 == 0 ? P.ns : 0);  // + the super-diagonal workgroups
+    hipLaunchKernelGGL((k_sym<MODE, LOCAL>), dim3(grid), dim3(64 * P.W), lds, st, a);
+    if (c0 + nc >= P.C) mark(g_ev_stop, st);
+    if (ESUM && e_total) {
+      // the first batch's sum includes the super-diagonal sums stored before it
+      const double* part = b == 0 ? P.ep : P.ep + P.ns;
+      const int m = P.G * nc + (b == 0 ? P.ns : 0);
+      sum_blocks(part, m, nbatch == 1 ? e_total : P.eb + b, st);
+    }
+    if (JSIDE) {
+      r.c0 = c0;
+      r.nc = nc;
+      r.first = c0 == 0;
+      r.last = c0 + nc >= P.C;
+      hipLaunchKernelGGL((k_sym_reduce<MODE>), dim3(P.ns), dim3(2 * SB),
+                         (size_t)nc * P.mj * sizeof(int32_t), st, r);
+    }
+  }
+  if (e_total) {
+    if (MODE == kEnergy && LOCAL) sum_blocks(P.eblk, P.ns, e_total, st);
+    else if (ESUM && nbatch > 1) sum_blocks(P.eb, nbatch, e_total, st);
+  }
 }
 
 template <int MODE>
@@ -838,12 +1180,12 @@ int coulomb_energy(const double* x, const double* y, int64_t n, int precision, d
   hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
   if (precision == CD_MIXED) {
-    if (e_local) run_sym<kEnergy, true>(P, st, e_local, nullptr);
-    else run_sym<kEnergy, false>(P, st, nullptr, nullptr);
+    if (e_local) run_sym<kEnergy, true>(P, st, e_local, nullptr, e_total);
+    else run_sym<kEnergy, false>(P, st, nullptr, nullptr, e_total);
   } else {
     run_one64<kEnergy>(P, st, e_local, nullptr);
+    sum_blocks(P.eblk, P.nred, e_total, st);
   }
-  hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, st, P.eblk, P.nred, e_total);
   return hip_status(hipGetLastError());
 }
 
@@ -855,10 +1197,12 @@ int coulomb_forces(const double* x, const double* y, int64_t n, int precision, d
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
-  if (precision == CD_MIXED) run_sym<kForces, false>(P, st, fx, fy);
-  else run_one64<kForces>(P, st, fx, fy);
-  if (e_total)
-    hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, st, P.eblk, P.nred, e_total);
+  if (precision == CD_MIXED) {
+    run_sym<kForces, false>(P, st, fx, fy, e_total);
+  } else {
+    run_one64<kForces>(P, st, fx, fy);
+    if (e_total) sum_blocks(P.eblk, P.nred, e_total, st);
+  }
   return hip_status(hipGetLastError());
 }
 
@@ -870,7 +1214,7 @@ int coulomb_hvp(const double* x, const double* y, const double* vx, const double
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, vx, vy, st))) return rc;
-  if (precision == CD_MIXED) run_sym<kHvp, false>(P, st, hx, hy);
+  if (precision == CD_MIXED) run_sym<kHvp, false>(P, st, hx, hy, nullptr);
   else run_one64<kHvp>(P, st, hx, hy);
   return hip_status(hipGetLastError());
 }

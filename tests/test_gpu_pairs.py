@@ -122,6 +122,39 @@ def test_full_size_workload3_sampled(dev, prec):
     assert abs(fx.sum()) <= 1e-6 * scale and abs(fy.sum()) <= 1e-6 * scale
 
 
+def test_mixed_large_n_batched(dev):
+    # N = 400000: the symmetric pass runs its chunks in several batches (the
+    # partial sums of one batch are capped at 512 MiB), each reduced and added
+    # to the outputs before the next.  Sampled rows against the oracle, local
+    # energies summing to the total, Euler's identity.
+    x, y = W.warped_lattice(400000, 0.02, 1404)
+    n = x.size
+    print(f"[case] lattice n={n} mixed batched", flush=True)
+    ws_full = (((n + 127) // 128 * 128) + ((n + 127) // 128 + 7) // 8 * 19 * 128) * 16 * (
+        ((n + 127) // 128 // 2 + 11) // 12)
+    assert ops.lib().coulomb_workspace_bytes(ops.OP_FORCES, n, 0, 0, MIXED) < ws_full // 2
+    xt, yt = t(x, dev), t(y, dev)
+    vx, vy = W.unit_vector(n, 1405)
+    tol = TOL[MIXED]
+    fx, fy, E = ops.forces(xt, yt, MIXED)
+    E2, e = ops.energy(xt, yt, MIXED, local=True)
+    hx, hy = ops.hvp(xt, yt, t(vx, dev), t(vy, dev), MIXED)
+    torch.cuda.synchronize()
+    fx, fy, e, hx, hy = (a.cpu().numpy() for a in (fx, fy, e, hx, hy))
+    rows = np.sort(np.random.default_rng(11).choice(n, 256, replace=False)).astype(np.int32)
+    ofx, ofy, oe = O.rows(x, y, rows)
+    ohx, ohy, _ = O.rows(x, y, rows, vx, vy)
+    errF = rel_rms(fx[rows], fy[rows], ofx, ofy)
+    erre = np.max(np.abs(e[rows] - oe) / oe)
+    errH = rel_rms(hx[rows], hy[rows], ohx, ohy)
+    Esum = np.sum(e)
+    errE = max(abs(E.item() - Esum), abs(E2.item() - Esum)) / Esum
+    euler = abs(np.sum(x * fx + y * fy) - Esum) / Esum
+    print(f"[err] lattice400k e={erre:.2e} F={errF:.2e} H={errH:.2e} E~sum(e)={errE:.2e} euler={euler:.2e}")
+    assert errF <= tol["F"] and erre <= tol["e"] and errH <= tol["H"]
+    assert errE <= tol["E"] and euler <= 10 * tol["F"]
+
+
 def test_validate_flags(dev):
     x, y = W.uniform_disk(300, 9)
     x[3], y[3] = np.nan, 0.0
