@@ -19,11 +19,13 @@ Printed: one JSON line with the driver's fields plus
                 per-patch energy agreement (same minimum: E_sub to 1e-12).
 
 Other modes: --cycles K runs K perturb-and-relax cycles (64 kicked patches
-each, greedy commit) and prints energy versus wall time; --copy-probe runs a
+each, greedy commit) and prints energy versus wall time; --relax-only mixed|fp64
+times one relax call on the 256 patches of workload 4; --copy-probe runs a
 plain device copy of known size (to calibrate HBM byte counters).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
-                       [--no-relax] [--cycles K --cycle-n N] [--copy-probe]
+                       [--no-relax] [--cycles K --cycle-n N] [--relax-only mixed|fp64]
+                       [--copy-probe]
 """
 import argparse
 import ctypes
@@ -159,6 +161,30 @@ def relax_comparison(xt, yt, subset):
     }
 
 
+def relax_only(dev, prec):
+    """One relax_subdomains call on the 256 patches of workload 4 (for profiles)."""
+    import numpy as np
+    import torch
+    from paper_2609_24722_amd import workloads as W
+    from paper_2609_24722_amd import relax as R
+    x, y = W.workload(4)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+    centres, sizes = W.patch_draws(x.size, 256, 200, 5000, 1104)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    it = r.iters.cpu().numpy()
+    print(json.dumps({"relax_precision": "mixed" if prec else "fp64", "patches": 256,
+                      "actives": int(ptr[-1]), "seconds": dt,
+                      "status": np.bincount(r.status.cpu().numpy(), minlength=4).tolist(),
+                      "iterations_mean": float(it[:, 0].mean()), "iterations_max": int(it[:, 0].max()),
+                      "exact_passes_mean": float(it[:, 1].mean())}), flush=True)
+
+
 def copy_probe(dev):
     """A plain device-to-device copy of 512 MiB, three times (for counters)."""
     import torch
@@ -217,6 +243,8 @@ def main():
     ap.add_argument("--cycles", type=int, default=0)
     ap.add_argument("--cycle-n", type=int, default=40000)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
+                    help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the all-pairs pass shards by i-range across GPUs "
@@ -232,6 +260,9 @@ def main():
         return
     if args.cycles > 0:
         cycles_mode(dev, args.cycles, args.cycle_n)
+        return
+    if args.relax_only:
+        relax_only(dev, MIXED if args.relax_only == "mixed" else FP64)
         return
     lib = ops.lib()
     lib.coulomb_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]

@@ -486,7 +486,7 @@ __global__ void k_exact_sum(RelaxDev R, int grad) {
 //   E_i = 1/2 sum_A 1/r + sum_halo 1/r + f.d + 1/2 d.H d,  d = z_i - zr_i
 // Per patch either FP32 pairs (coordinates relative to the patch centre,
 // partials of at most 64 terms folded into FP64) or FP64 pairs.
-template <bool SELF>
+template <bool SELF, bool WK>
 __device__ __forceinline__ void pairs32(const float* __restrict__ xs, const float* __restrict__ ys,
                                         int b0, int b1, int self, float xf, float yf, double& G0,
                                         double& G1, double& E, double* K, double w) {
@@ -503,10 +503,12 @@ __device__ __forceinline__ void pairs32(const float* __restrict__ xs, const floa
       e += inv;
       g0 = __builtin_fmaf(-dx, i3, g0);
       g1 = __builtin_fmaf(-dy, i3, g1);
-      const float t3 = 3.0f * i3 * inv * inv;
-      k0 += __builtin_fmaf(t3 * dx, dx, -i3);
-      k1 += t3 * dx * dy;
-      k2 += __builtin_fmaf(t3 * dy, dy, -i3);
+      if (WK) {
+        const float t3 = 3.0f * i3 * inv * inv;
+        k0 += __builtin_fmaf(t3 * dx, dx, -i3);
+        k1 += t3 * dx * dy;
+        k2 += __builtin_fmaf(t3 * dy, dy, -i3);
+      }
     }
     G0 += g0;
     G1 += g1;
@@ -517,7 +519,7 @@ __device__ __forceinline__ void pairs32(const float* __restrict__ xs, const floa
   }
 }
 
-template <bool SELF>
+template <bool SELF, bool WK>
 __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
                                         const double* __restrict__ ys, int b0, int b1, int self,
                                         double xi, double yi, double& G0, double& G1, double& E,
@@ -535,10 +537,12 @@ __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
       e += inv;
       G0 = __builtin_fma(-dx, i3, G0);
       G1 = __builtin_fma(-dy, i3, G1);
-      const double t3 = 3.0 * i3 * inv * inv;
-      K[0] += __builtin_fma(t3 * dx, dx, -i3);
-      K[1] += t3 * dx * dy;
-      K[2] += __builtin_fma(t3 * dy, dy, -i3);
+      if (WK) {
+        const double t3 = 3.0 * i3 * inv * inv;
+        K[0] += __builtin_fma(t3 * dx, dx, -i3);
+        K[1] += t3 * dx * dy;
+        K[2] += __builtin_fma(t3 * dy, dy, -i3);
+      }
     }
     const double v = w * e;
     const double tt = E + v;
@@ -547,43 +551,76 @@ __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
   }
 }
 
-__global__ __launch_bounds__(256) void k_model(RelaxDev R) {
-  // the wave index is uniform within a wave; saying so lets the compiler keep
-  // patch data in SGPRs and read the j charges through the scalar cache
-  const int wb = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+// One workgroup per 64-active block; its kMW waves split the patch's j list
+// (actives, then halo) into ranges cut at multiples of 64 and the partial
+// sums are combined in LDS in wave order, so a large patch spreads over
+// kMW times more waves when few patches are still running.
+constexpr int kMW = 8;
+
+template <bool WK>
+__global__ __launch_bounds__(64 * kMW) void k_model(RelaxDev R) {
+  __shared__ double part[kMW][7][64];  // G0 G1 E Ec K0 K1 K2 per wave and lane
+  const int wb = blockIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wb >= R.nblk) return;
   const int2 bk = R.blk[wb];
   const int p = bk.x;
   const PState& st = R.st[p];
-  if (!R.eval_all && st.status != kRunning) return;
+  if (!R.eval_all && st.status != kRunning) return;  // the same for the whole workgroup
   const bool use32 = st.use32;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
+  const int na = a1 - a0, nj = na + (h1 - h0);
+  const int per = ((nj + kMW - 1) / kMW + 63) & ~63;
+  const int j0 = min(nj, w * per), j1 = min(nj, j0 + per);
   const int a = bk.y + lane;
   const bool ok = a < a1;
   const int ac = ok ? a : a1 - 1;
   const double xi = R.tx[ac], yi = R.ty[ac];
-  double G0 = 0.0, G1 = 0.0, E = 0.0, K[3] = {0.0, 0.0, 0.0};
+  double G0 = 0.0, G1 = 0.0, E = 0.0, Ec = 0.0, K[3] = {0.0, 0.0, 0.0};
   if (use32) {
     const float xf = R.a32x[ac], yf = R.a32y[ac];
-    pairs32<true>(R.a32x, R.a32y, a0, a1, ac, xf, yf, G0, G1, E, K, 0.5);
-    pairs32<false>(R.h32x, R.h32y, h0, h1, -1, xf, yf, G0, G1, E, K, 1.0);
+    pairs32<true, WK>(R.a32x, R.a32y, a0 + j0, a0 + min(j1, na), ac, xf, yf, G0, G1, E, K, 0.5);
+    pairs32<false, WK>(R.h32x, R.h32y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, xf, yf, G0,
+                   G1, E, K, 1.0);
   } else {
-    double Ec = 0.0;
-    pairs64<true>(R.tx, R.ty, a0, a1, ac, xi, yi, G0, G1, E, Ec, K, 0.5);
-    pairs64<false>(R.h64x, R.h64y, h0, h1, -1, xi, yi, G0, G1, E, Ec, K, 1.0);
-    E += Ec;
+    pairs64<true, WK>(R.tx, R.ty, a0 + j0, a0 + min(j1, na), ac, xi, yi, G0, G1, E, Ec, K, 0.5);
+    pairs64<false, WK>(R.h64x, R.h64y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, xi, yi, G0,
+                   G1, E, Ec, K, 1.0);
   }
-  if (!ok) return;
+  part[w][0][lane] = G0;
+  part[w][1][lane] = G1;
+  part[w][2][lane] = E;
+  part[w][3][lane] = Ec;
+  part[w][4][lane] = K[0];
+  part[w][5][lane] = K[1];
+  part[w][6][lane] = K[2];
+  __syncthreads();
+  if (w != 0 || !ok) return;
+  G0 = G1 = E = Ec = 0.0;
+  K[0] = K[1] = K[2] = 0.0;
+  for (int q = 0; q < kMW; ++q) {
+    G0 += part[q][0][lane];
+    G1 += part[q][1][lane];
+    const double v = part[q][2][lane], tt = E + v;  // Neumaier across the waves' sums
+    Ec += (fabs(E) >= fabs(v) ? (E - tt) + v : (v - tt) + E) + part[q][3][lane];
+    E = tt;
+    K[0] += part[q][4][lane];
+    K[1] += part[q][5][lane];
+    K[2] += part[q][6][lane];
+  }
+  E += Ec;
   const double ddx = xi - R.zrx[a], ddy = yi - R.zry[a];
   const double hx = R.fhxx[a] * ddx + R.fhxy[a] * ddy, hy = R.fhxy[a] * ddx + R.fhyy[a] * ddy;
   E += R.fgx[a] * ddx + R.fgy[a] * ddy + 0.5 * (ddx * hx + ddy * hy);
   R.hgx[a] = G0 + R.fgx[a] + hx;
   R.hgy[a] = G1 + R.fgy[a] + hy;
-  R.hkxx[a] = K[0] + R.fhxx[a];
-  R.hkxy[a] = K[1] + R.fhxy[a];
-  R.hkyy[a] = K[2] + R.fhyy[a];
+  if (WK) {
+    R.hkxx[a] = K[0] + R.fhxx[a];
+    R.hkxy[a] = K[1] + R.fhxy[a];
+    R.hkyy[a] = K[2] + R.fhyy[a];
+  }
   R.eterm[a] = E;
 }
 
@@ -617,21 +654,28 @@ __global__ void k_model_prep(RelaxDev R, int halo_too) {
 // gradient decrease when the energy change is below the evaluation's noise),
 // update the L-BFGS history and the wall-held set, test convergence, and
 // form the next trial point.
-constexpr int kUpd = 256;
+constexpr int kUpd = 1024;
+constexpr int kUpdWaves = kUpd / 64;
+constexpr int kRegJ = 4;  // actives per thread held in registers by the two-loop
 
+// Workgroup sum and maximum (fixed order: waves' results in wave order).
 __device__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  double t = 0.0;
+  for (int q = 0; q < kUpdWaves; ++q) t += red[q];
+  return t;
 }
 __device__ double block_max(double v, double* red) {
   v = wave_max(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  double t = red[0];
+  for (int q = 1; q < kUpdWaves; ++q) t = fmax(t, red[q]);
+  return t;
 }
 
 // reduced gradient component magnitude at position (px, py) with gradient g:
@@ -729,8 +773,16 @@ __device__ void apply_prec(bool held, double px, double py, double g0, double g1
   r1 = vy * (p1 / l1) + vx * (p2 / l2);
 }
 
+// HT: storage type of the L-BFGS history (FP32 on the mixed path, where it
+// halves the kernel's dominant memory traffic; FP64 on the plain path).  The
+// recursion itself runs in FP64.
+template <class HT>
 __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
-  __shared__ double red[4];
+  HT* const Sx = reinterpret_cast<HT*>(R.Sx);
+  HT* const Sy = reinterpret_cast<HT*>(R.Sy);
+  HT* const Yx = reinterpret_cast<HT*>(R.Yx);
+  HT* const Yy = reinterpret_cast<HT*>(R.Yy);
+  __shared__ double red[kUpdWaves];
   __shared__ double s_alf[kMaxMem];
   __shared__ int s_flag;
   const int p = blockIdx.x, t = threadIdx.x;
@@ -806,12 +858,16 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         }
         coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
         coord_grad(h, R.tx[a], R.ty[a], R.hgx[a], R.hgy[a], n0, n1);
-        const double y0 = n0 - c0, y1 = n1 - c1;
+        // the pair as stored (rounded to HT), so that rho matches the vectors
+        const HT hs0 = (HT)s0, hs1 = (HT)s1, hy0 = (HT)(n0 - c0), hy1 = (HT)(n1 - c1);
         const size_t q = (size_t)k * R.ntot + a;
-        R.Sx[q] = s0;
-        R.Sy[q] = s1;
-        R.Yx[q] = y0;
-        R.Yy[q] = y1;
+        Sx[q] = hs0;
+        Sy[q] = hs1;
+        Yx[q] = hy0;
+        Yy[q] = hy1;
+        s0 = hs0;
+        s1 = hs1;
+        const double y0 = hy0, y1 = hy1;
         syp += s0 * y0 + s1 * y1;
         ssp += s0 * s0 + s1 * s1;
         yyp += y0 * y0 + y1 * y1;
@@ -842,7 +898,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         if (!s.init) {
           for (int k = 0; k < m; ++k) {
             const size_t q = (size_t)k * R.ntot + a;
-            R.Sx[q] = R.Sy[q] = R.Yx[q] = R.Yy[q] = 0.0;
+            Sx[q] = Sy[q] = Yx[q] = Yy[q] = (HT)0;
           }
         }
         s_flag = 1;
@@ -857,7 +913,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         double sy = 0.0;
         for (int a = a0 + t; a < a1; a += kUpd) {
           const size_t q = (size_t)kk * R.ntot + a;
-          sy += R.Sx[q] * R.Yx[q] + R.Sy[q] * R.Yy[q];
+          sy += (double)Sx[q] * (double)Yx[q] + (double)Sy[q] * (double)Yy[q];
         }
         sy = block_sum(sy, red);
         if (t == 0) rho[kk] = sy > 0.0 ? 1.0 / sy : 0.0;
@@ -903,54 +959,148 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     s.head = 0;
   }
 
-  // new direction: two-loop recursion on the coordinate gradient
+  // new direction: two-loop recursion on the coordinate gradient.  For a
+  // patch of at most kRegJ * kUpd actives the vector stays in registers and
+  // each history pair is loaded once per loop, both halves issued before the
+  // reduction; larger patches keep it in memory.  Same arithmetic, same order.
   __syncthreads();
-  for (int a = a0 + t; a < a1; a += kUpd) {
-    double c0, c1;
-    coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
-    R.dx[a] = c0;
-    R.dy[a] = c1;
-  }
-  __syncthreads();
-  for (int k = 0; k < s.mem; ++k) {
-    const int kk = (s.head - 1 - k + m) % m;
-    double v = 0.0;
-    for (int a = a0 + t; a < a1; a += kUpd) {
-      const size_t q = (size_t)kk * R.ntot + a;
-      v += R.Sx[q] * R.dx[a] + R.Sy[q] * R.dy[a];
+  if (a1 - a0 <= kRegJ * kUpd) {
+    double qx[kRegJ], qy[kRegJ];
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) {
+      const int a = a0 + t + j * kUpd;
+      qx[j] = qy[j] = 0.0;
+      if (a < a1) coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], qx[j], qy[j]);
     }
-    const double al = rho[kk] * block_sum(v, red);
-    if (t == 0) s_alf[kk] = al;
+    for (int k = 0; k < s.mem; ++k) {
+      const int kk = (s.head - 1 - k + m) % m;
+      const size_t base = (size_t)kk * R.ntot;
+      HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) {
+        const int a = a0 + t + j * kUpd;
+        const bool ok = a < a1;
+        ux[j] = ok ? Sx[base + a] : (HT)0;
+        uy[j] = ok ? Sy[base + a] : (HT)0;
+        wx[j] = ok ? Yx[base + a] : (HT)0;
+        wy[j] = ok ? Yy[base + a] : (HT)0;
+      }
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
+      const double al = rho[kk] * block_sum(v, red);
+      if (t == 0) s_alf[kk] = al;
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) {
+        qx[j] -= al * (double)wx[j];
+        qy[j] -= al * (double)wy[j];
+      }
+    }
+    // the preconditioner goes through memory (a loop, not unrolled: its
+    // temporaries would not fit beside the register-held vector)
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) {
+      const int a = a0 + t + j * kUpd;
+      if (a < a1) {
+        R.dx[a] = qx[j];
+        R.dy[a] = qy[j];
+      }
+    }
     for (int a = a0 + t; a < a1; a += kUpd) {
-      const size_t q = (size_t)kk * R.ntot + a;
-      R.dx[a] -= al * R.Yx[q];
-      R.dy[a] -= al * R.Yy[q];
+      double r0, r1;
+      apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
+                 R.dx[a], R.dy[a], r0, r1);
+      R.dx[a] = r0;
+      R.dy[a] = r1;
+    }
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) {
+      const int a = a0 + t + j * kUpd;
+      if (a < a1) {
+        qx[j] = R.dx[a];
+        qy[j] = R.dy[a];
+      }
+    }
+    for (int k = s.mem - 1; k >= 0; --k) {
+      const int kk = (s.head - 1 - k + m) % m;
+      const size_t base = (size_t)kk * R.ntot;
+      HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) {
+        const int a = a0 + t + j * kUpd;
+        const bool ok = a < a1;
+        wx[j] = ok ? Yx[base + a] : (HT)0;
+        wy[j] = ok ? Yy[base + a] : (HT)0;
+        ux[j] = ok ? Sx[base + a] : (HT)0;
+        uy[j] = ok ? Sy[base + a] : (HT)0;
+      }
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
+      const double be = rho[kk] * block_sum(v, red);
+      const double coef = s_alf[kk] - be;
+#pragma unroll
+      for (int j = 0; j < kRegJ; ++j) {
+        qx[j] += coef * (double)ux[j];
+        qy[j] += coef * (double)uy[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) {
+      const int a = a0 + t + j * kUpd;
+      if (a < a1) {
+        R.dx[a] = qx[j];
+        R.dy[a] = qy[j];
+      }
+    }
+  } else {
+    for (int a = a0 + t; a < a1; a += kUpd) {
+      double c0, c1;
+      coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      R.dx[a] = c0;
+      R.dy[a] = c1;
     }
     __syncthreads();
-  }
-  for (int a = a0 + t; a < a1; a += kUpd) {
-    double r0, r1;
-    apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
-               R.dx[a], R.dy[a], r0, r1);
-    R.dx[a] = r0;
-    R.dy[a] = r1;
-  }
-  __syncthreads();
-  for (int k = s.mem - 1; k >= 0; --k) {
-    const int kk = (s.head - 1 - k + m) % m;
-    double v = 0.0;
-    for (int a = a0 + t; a < a1; a += kUpd) {
-      const size_t q = (size_t)kk * R.ntot + a;
-      v += R.Yx[q] * R.dx[a] + R.Yy[q] * R.dy[a];
+    for (int k = 0; k < s.mem; ++k) {
+      const int kk = (s.head - 1 - k + m) % m;
+      double v = 0.0;
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        const size_t q = (size_t)kk * R.ntot + a;
+        v += (double)Sx[q] * R.dx[a] + (double)Sy[q] * R.dy[a];
+      }
+      const double al = rho[kk] * block_sum(v, red);
+      if (t == 0) s_alf[kk] = al;
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        const size_t q = (size_t)kk * R.ntot + a;
+        R.dx[a] -= al * (double)Yx[q];
+        R.dy[a] -= al * (double)Yy[q];
+      }
+      __syncthreads();
     }
-    const double be = rho[kk] * block_sum(v, red);
-    const double coef = s_alf[kk] - be;
     for (int a = a0 + t; a < a1; a += kUpd) {
-      const size_t q = (size_t)kk * R.ntot + a;
-      R.dx[a] += coef * R.Sx[q];
-      R.dy[a] += coef * R.Sy[q];
+      double r0, r1;
+      apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
+                 R.dx[a], R.dy[a], r0, r1);
+      R.dx[a] = r0;
+      R.dy[a] = r1;
     }
     __syncthreads();
+    for (int k = s.mem - 1; k >= 0; --k) {
+      const int kk = (s.head - 1 - k + m) % m;
+      double v = 0.0;
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        const size_t q = (size_t)kk * R.ntot + a;
+        v += (double)Yx[q] * R.dx[a] + (double)Yy[q] * R.dy[a];
+      }
+      const double be = rho[kk] * block_sum(v, red);
+      const double coef = s_alf[kk] - be;
+      for (int a = a0 + t; a < a1; a += kUpd) {
+        const size_t q = (size_t)kk * R.ntot + a;
+        R.dx[a] += coef * (double)Sx[q];
+        R.dy[a] += coef * (double)Sy[q];
+      }
+      __syncthreads();
+    }
   }
   // d = -H g; fall back to scaled steepest descent if not a descent direction
   double dg = 0.0, dm = 0.0;
@@ -1034,7 +1184,7 @@ __global__ void k_count_running(RelaxDev R) {
 // of their current exact gradient.
 __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double frac,
                                                 double tol32, double* __restrict__ ptol) {
-  __shared__ double red[4];
+  __shared__ double red[kUpdWaves];
   const int p = blockIdx.x, t = threadIdx.x;
   PState s = R.st[p];
   if (s.status == kNonFinite || s.status == kDone) return;
@@ -1062,7 +1212,7 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
                                                  double* __restrict__ gtan,
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ status) {
-  __shared__ double red[4];
+  __shared__ double red[kUpdWaves];
   const int p = blockIdx.x, t = threadIdx.x;
   const PState s = R.st[p];
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
@@ -1091,7 +1241,7 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
 }
 
 __global__ __launch_bounds__(kUpd) void k_finish_delta(RelaxDev R, double* __restrict__ dE) {
-  __shared__ double red[4];
+  __shared__ double red[kUpdWaves];
   const int p = blockIdx.x, t = threadIdx.x;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   double e = 0.0;
@@ -1219,14 +1369,17 @@ static int g_last_rounds = 0;
 static bool g_trace = false;  // CD_RELAX_TRACE set: progress lines on stderr
 
 template <class EvalFn>
-static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, EvalFn eval) {
+static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, EvalFn eval) {
   RelaxDev& D = R.D;
   int32_t h_running = 0;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
   for (int r = 0; r < max_rounds; ++r) {
     g_last_rounds = r + 1;
     eval();
-    hipLaunchKernelGGL(k_update, dim3(R.P), dim3(kUpd), 0, st, D);
+    if (hist32)
+      hipLaunchKernelGGL(k_update<float>, dim3(R.P), dim3(kUpd), 0, st, D);
+    else
+      hipLaunchKernelGGL(k_update<double>, dim3(R.P), dim3(kUpd), 0, st, D);
     if ((r & 7) == 7) {
       if (hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
           hipSuccess)
@@ -1367,7 +1520,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
 
   if (o.precision == CD_FP64) {
     D.tol = o.gtol;
-    if ((rc = run_rounds(R, st, max_rounds, [&]() { exact_grad(0); }))) return rc;
+    if ((rc = run_rounds(R, st, max_rounds, false, [&]() { exact_grad(0); }))) return rc;
   } else {
     const double w = (o.halo_width > 0.0 ? o.halo_width : 4.0) * h;
     hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 0, R.hcount);
@@ -1393,7 +1546,12 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       RelaxDev E = D;
       E.eval_all = all;
       hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
-      hipLaunchKernelGGL(k_model, dim3((D.nblk + 3) / 4), eb, 0, st, E);
+      // the Hessian blocks (preconditioner) are evaluated at the expansion
+      // point only and kept for the rest of the round
+      if (all)
+        hipLaunchKernelGGL(k_model<true>, dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+      else
+        hipLaunchKernelGGL(k_model<false>, dim3(D.nblk), dim3(64 * kMW), 0, st, E);
     };
     // rounds: expand the far field exactly at z (one O(n_act N) FP64 pass);
     // the model gradient at its expansion point is the exact gradient, which
@@ -1435,7 +1593,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       }
       if (hr == 0) break;
       D.ptol = ptol_ws;
-      rc = run_rounds(R, st, max_rounds, [&]() { model(0); });
+      rc = run_rounds(R, st, max_rounds, true, [&]() { model(0); });
       D.ptol = nullptr;
       if (rc) return rc;
     }
