@@ -164,7 +164,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
  * committed[P] (host int32): 1 if committed; dE_commit[P] (host): the
  * re-evaluated change (0 when not evaluated).  ws: at least
  * coulomb_workspace_bytes(CD_OP_RELAX, n, 1, largest patch, CD_FP64) + 512
- * bytes.  Synchronises the stream. */
+ * bytes (the CD_OP_RELAX size never decreases as total_active grows, so this
+ * covers every patch).  Synchronises the stream. */
 int commit_patches(double* x, double* y, int64_t n, int32_t n_patches, const int32_t* patch_ptr,
                    const int32_t* active_idx, const double* x_rel, const double* y_rel,
                    const double* order_key, int32_t* committed, double* dE_commit, void* ws,

@@ -1278,6 +1278,11 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   cv.base = base;
   RelaxDev& D = R.D;
   const size_t nt = R.ntot;
+  // split partials hold nt * splits values; since splits <= ceil(16384 / nblk)
+  // and nblk > nt / 64 that is below 16384 * 64 + nt, a bound that grows with
+  // nt, so the workspace of a larger batch covers every smaller one (the
+  // greedy commit sizes its scratch for the largest patch)
+  const size_t pcap = (size_t)16384 * 64 + nt;
   D.pid = cv.take<int32_t>(nt);
   D.blk = cv.take<int2>(R.nblk);
   D.maskA = cv.take<uint64_t>((size_t)P * R.nbN);
@@ -1298,9 +1303,9 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.hkxx = cv.take<double>(nt);
   D.hkxy = cv.take<double>(nt);
   D.hkyy = cv.take<double>(nt);
-  D.pkxx = cv.take<double>(nt * R.splits);
-  D.pkxy = cv.take<double>(nt * R.splits);
-  D.pkyy = cv.take<double>(nt * R.splits);
+  D.pkxx = cv.take<double>(pcap);
+  D.pkxy = cv.take<double>(pcap);
+  D.pkyy = cv.take<double>(pcap);
   D.dx = cv.take<double>(nt);
   D.dy = cv.take<double>(nt);
   D.Sx = cv.take<double>(nt * m);
@@ -1310,9 +1315,9 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.rho = cv.take<double>((size_t)P * m);
   D.held = cv.take<int32_t>(nt);
   D.eterm = cv.take<double>(nt);
-  D.px = cv.take<double>(nt * R.splits);
-  D.py = cv.take<double>(nt * R.splits);
-  D.pe = cv.take<double>(nt * R.splits);
+  D.px = cv.take<double>(pcap);
+  D.py = cv.take<double>(pcap);
+  D.pe = cv.take<double>(pcap);
   D.st = cv.take<PState>(P);
   D.ptr_w = cv.take<int32_t>(P + 1);
   D.ptol = cv.take<double>(P);

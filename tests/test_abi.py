@@ -54,6 +54,20 @@ def test_workspace_sizes_are_host_computable(L):
     assert f(1, 100, 0, 0, 7) == 0        # bad precision
 
 
+def test_relax_workspace_grows_with_patch_size(L):
+    # commit_patches sizes its scratch for the largest patch and evaluates
+    # each patch in it, so a smaller patch must never need more (a 127-charge
+    # patch once needed more than a 128-charge one).
+    f = L.coulomb_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int]
+    for n in (5000, 40000, 100000):
+        for prec in (0, 1):
+            sizes = [f(5, n, 1, k, prec) for k in range(1, 4097)]
+            assert all(s > 0 for s in sizes)
+            assert all(b >= a for a, b in zip(sizes, sizes[1:])), (n, prec)
+
+
 def test_argument_errors_before_any_launch(L):
     vp = ctypes.c_void_p
     L.coulomb_forces.restype = ctypes.c_int

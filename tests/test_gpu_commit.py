@@ -61,3 +61,37 @@ def test_commit_matches_oracle_greedy(dev):
     assert np.array_equal(xt.cpu().numpy(), X) and np.array_equal(yt.cpu().numpy(), Y)
     # tracked energy vs a from-scratch evaluation (drift check)
     assert abs((E0 + d[c == 1].sum()) - O.energy(X, Y)) <= 1e-12 * E0
+
+
+def test_commit_patch_sizes_across_block_boundary(dev):
+    # patches of 127 and 128 charges: the scratch sized for the largest patch
+    # must hold the evaluation of every smaller one
+    n = 4000
+    x, y = W.warped_lattice(n, 0.1, 51)
+    h = W.spacing(n)
+    sizes = np.array([128, 127, 63, 65], dtype=np.int32)
+    centres = np.array([100, 1500, 2500, 3500], dtype=np.int32)
+    idx = O.patches(x, y, centres, sizes)
+    ptr = np.zeros(sizes.size + 1, dtype=np.int32)
+    ptr[1:] = np.cumsum(sizes)
+    kx, ky = W.kicks(idx.size, 0.05 * h, 52)
+    xr, yr = x[idx] + kx, y[idx] + ky
+    rr = np.hypot(xr, yr)
+    xr, yr = np.where(rr > 1, xr / rr, xr), np.where(rr > 1, yr / rr, yr)
+    key = -np.arange(1.0, sizes.size + 1)  # every candidate is tried, largest first
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+    c, d = R.commit_patches(xt, yt, ptr, torch.tensor(idx, device=dev), torch.tensor(xr, device=dev),
+                            torch.tensor(yr, device=dev), key)
+    torch.cuda.synchronize()
+    # reference: the same greedy order on the oracle (the patches are disjoint,
+    # so every candidate is evaluated, against the configuration as committed)
+    X, Y = x.copy(), y.copy()
+    ref_d = np.zeros(sizes.size)
+    for p in np.argsort(key, kind="stable"):
+        sl = slice(ptr[p], ptr[p + 1])
+        ref_d[p] = O.esub_delta(X, Y, idx[sl], xr[sl], yr[sl])
+        if ref_d[p] < 0:
+            X[idx[sl]], Y[idx[sl]] = xr[sl], yr[sl]
+    assert np.array_equal(c, (ref_d < 0).astype(np.int32)) and 0 < c.sum() < sizes.size
+    np.testing.assert_allclose(d, ref_d, rtol=1e-9, atol=1e-9)
