@@ -133,6 +133,31 @@ def relax_comparison(xt, yt, subset):
     t_mix, r_mix = run(ps, ids, MIXED)
     t_fp, r_fp = run(ps, ids, FP64)
     h = W.spacing(n)
+    # same basin: both paths from the plain path's endpoints kicked by 0.02 h
+    # (seeded), so that they end in one minimum and the times compare at equal E
+    rng = np.random.default_rng(1204)
+    m = int(ps[-1])
+    bx = r_fp.x.cpu().numpy() + rng.normal(0.0, 0.02 * h, m)
+    by = r_fp.y.cpu().numpy() + rng.normal(0.0, 0.02 * h, m)
+    rr = np.hypot(bx, by)
+    bx, by = np.where(rr > 1, bx / rr, bx), np.where(rr > 1, by / rr, by)
+    sxt, syt = torch.tensor(bx, device=xt.device), torch.tensor(by, device=xt.device)
+
+    def run_from(prec):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = R.relax_subdomains(xt, yt, ps, ids, sxt, syt, precision=prec, gtol=1e-3)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    tb_mix, rb_mix = run_from(MIXED)
+    tb_fp, rb_fp = run_from(FP64)
+    ebm, ebf = rb_mix.e_sub.cpu().numpy(), rb_fp.e_sub.cpu().numpy()
+    dbx = np.array([np.hypot(rb_mix.x.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.x.cpu().numpy()[ps[p]:ps[p + 1]],
+                             rb_mix.y.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.y.cpu().numpy()[ps[p]:ps[p + 1]]).max()
+                    for p in range(subset)])
+    bsame = dbx < 1e-3 * h
+    brel = np.abs(ebm - ebf) / np.abs(ebf)
     em, ef = r_mix.e_sub.cpu().numpy(), r_fp.e_sub.cpu().numpy()
     xm, ym, xf, yf = (a.cpu().numpy() for a in (r_mix.x, r_mix.y, r_fp.x, r_fp.y))
     disp = np.array([np.hypot(xm[ps[p]:ps[p + 1]] - xf[ps[p]:ps[p + 1]],
@@ -158,6 +183,14 @@ def relax_comparison(xt, yt, subset):
         "all_patches_median_rel_energy_diff": float(np.median(rel)),
         "mean_dE_mixed": float(r_mix.dE.mean().item()),
         "mean_dE_fp64": float(r_fp.dE.mean().item()),
+        "same_basin": {
+            "start": "the plain path's endpoints of the subset, kicked by N(0, (0.02 h)^2) per coordinate",
+            "mixed_s": tb_mix, "fp64_s": tb_fp, "speedup": tb_fp / tb_mix,
+            "same_minimum_patches": int(bsame.sum()),
+            "same_minimum_max_rel_energy_diff": float(brel[bsame].max()) if bsame.any() else None,
+            "max_rel_energy_diff_all": float(brel.max()),
+            "status_mixed": st(rb_mix), "status_fp64": st(rb_fp),
+        },
     }
 
 
