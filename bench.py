@@ -24,8 +24,8 @@ times one relax call on the 256 patches of workload 4; --copy-probe runs a
 plain device copy of known size (to calibrate HBM byte counters).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
-                       [--no-relax] [--cycles K --cycle-n N] [--relax-only mixed|fp64]
-                       [--copy-probe]
+                       [--no-relax] [--tune] [--cycles K --cycle-n N]
+                       [--relax-only mixed|fp64] [--copy-probe]
 """
 import argparse
 import ctypes
@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--cycles", type=int, default=0)
     ap.add_argument("--cycle-n", type=int, default=40000)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the pair pass's launch shape with coulomb_autotune before timing")
     ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
@@ -311,6 +313,8 @@ def main():
     vxt = torch.tensor(vx, device=dev)
     vyt = torch.tensor(vy, device=dev)
     torch.cuda.synchronize()
+    # launch shape of the pair pass: the library default, or the tuner's pick
+    shape = ops.autotune(xt, yt, ops.OP_FORCES) if args.tune else (0, 8, 12)
 
     step_ms, kern_ms = timed(lambda: ops.forces(xt, yt, MIXED), args.steps, args.warmup, lib, hip)
     value = pairs / (step_ms * 1e-3)
@@ -339,6 +343,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
+            "launch_shape": {"waves_per_workgroup": shape[1], "offsets_per_chunk": shape[2],
+                             "tuned": bool(args.tune)},
             "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -87,6 +87,21 @@ int coulomb_hvp(const double* x, const double* y, const double* vx, const double
                 int64_t n, int precision, double* hx, double* hy, void* ws, size_t ws_bytes,
                 void* stream);
 
+/* Launch-shape tuning of the CD_MIXED pair pass (not an operation of the
+ * paper; a performance setting).  Times each candidate shape of the
+ * symmetric pass (waves per workgroup, super-block offsets per chunk) for
+ * `op` (CD_OP_ENERGY, CD_OP_FORCES or CD_OP_HVP, the HVP with v = r) on the
+ * given positions, and keeps the fastest for later CD_MIXED calls with the
+ * same op and n on the current device (process-wide, thread-safe).  Results
+ * of those calls are deterministic for the chosen shape; another shape sums
+ * in another order (differences at FP32 rounding level).  shape_out: host
+ * int32[3] = chosen index, waves, offsets.  ws: at least
+ * coulomb_workspace_bytes(op, n, 0, 0, CD_MIXED) + 16 n + 512 bytes (the
+ * scratch of every pair call already covers all shapes).  Synchronises the
+ * stream. */
+int coulomb_autotune(const double* x, const double* y, int64_t n, int op, void* ws,
+                     size_t ws_bytes, void* stream, int32_t* shape_out);
+
 /* Domain check of positions against Eq. 3: flags_out[n] (int32) gets
  * CD_FLAG_* bits (non-finite; |r| > 1 + 4*2^-53; exactly coincident with
  * another charge).  *count_out (1 int32, device) = number of flagged
@@ -195,9 +210,10 @@ int tangent_lanczos(const double* x, const double* y, int64_t n, const int32_t* 
 
 /* Measurement hook: when ev_start/ev_stop (hipEvent_t passed as void*) are
  * non-NULL, every later energy/forces/HVP call records ev_start immediately
- * before and ev_stop immediately after its dominant pair kernel, on the
- * call's stream.  NULL, NULL disables.  Process-wide, not thread-safe; for
- * benchmarking only. */
+ * before its first and ev_stop immediately after its last launch of the
+ * dominant pair kernel, on the call's stream (with more than one batch of
+ * chunks the span includes the reductions between them).  NULL, NULL
+ * disables.  Process-wide, not thread-safe; for benchmarking only. */
 void coulomb_set_kernel_events(void* ev_start, void* ev_stop);
 
 /* Human-readable text for a return code (host string, static storage). */

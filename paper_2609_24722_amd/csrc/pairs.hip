@@ -12,6 +12,10 @@
 //                  CD_FP64: one-sided FP64 kernel over (i block, j range);
 //   3. reduction   fixed-order sums of the partial results, scattered back
 //                  to the caller's order; energy by a fixed-shape tree.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "plan.hpp"
 
 namespace cd {
@@ -891,8 +895,36 @@ __global__ void k_validate(const double* __restrict__ xs, const double* __restri
   if (f) atomicAdd(count, 1);
 }
 
+// ------------------------------------------------------------------ shapes --
+// Launch shapes of the symmetric pass (waves per workgroup W, offsets per
+// chunk L) that coulomb_autotune chooses from; the first is the default.  All
+// fit the kernel's launch bound (W <= kSymWaves) and the 64 KiB j window.
+struct SymShape {
+  int W, L;
+};
+constexpr SymShape kShapes[] = {{8, 12}, {8, 6},  {8, 8},  {8, 16}, {8, 20},
+                                {4, 8},  {4, 12}, {4, 16}, {4, 24}, {2, 24}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+static_assert(kShapes[0].W == kSymWaves && kShapes[0].L == kSymChunk, "default shape");
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int64_t>, int> g_tuned;  // (device, op, n) -> shape
+
+static int current_device() {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess) return -1;
+  return d;
+}
+
+static int tuned_shape(int op, int64_t n) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(dev, op, n));
+  return it == g_tuned.end() ? 0 : it->second;
+}
+
 // ---------------------------------------------------------------- planning --
-bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
+bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape) {
   if (n64 < 1 || n64 > (int64_t)1 << 26) return false;
   if (precision != CD_FP64 && precision != CD_MIXED) return false;
   const int n = (int)n64;
@@ -906,9 +938,12 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P) {
     P.npad = P.nb * kBlk;
     // W waves per workgroup, L offsets per chunk; S = L + W - 1 <= ns keeps
     // the j window from wrapping onto itself
-    P.W = P.ns < kSymWaves ? P.ns : kSymWaves;
+    if (shape < 0 || shape >= kNumShapes) shape = 0;
+    const SymShape sh = kShapes[shape];
+    P.shape = shape;
+    P.W = P.ns < sh.W ? P.ns : sh.W;
     const int l = P.ns + 1 - P.W;
-    P.L = l < 1 ? 1 : (l > kSymChunk ? kSymChunk : l);
+    P.L = l < 1 ? 1 : (l > sh.L ? sh.L : l);
     const int hmax = P.ns / 2;
     P.C = hmax > 0 ? (hmax + P.L - 1) / P.L : 1;
     P.G = (P.ns + P.W - 1) / P.W;
@@ -1154,30 +1189,38 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
   (void)n_patches;
   (void)total_active;
   if (op == CD_OP_ENERGY || op == CD_OP_FORCES || op == CD_OP_HVP || op == CD_OP_VALIDATE) {
-    Plan P;
-    if (!make_plan(op, n, op == CD_OP_VALIDATE ? CD_FP64 : precision, nullptr, P)) return 0;
-    return P.total;
+    const int prec = op == CD_OP_VALIDATE ? CD_FP64 : precision;
+    size_t most = 0;
+    // enough for every shape the tuner may choose
+    for (int sh = 0; sh < (prec == CD_MIXED ? kNumShapes : 1); ++sh) {
+      Plan P;
+      if (!make_plan(op, n, prec, nullptr, P, sh)) return 0;
+      most = P.total > most ? P.total : most;
+    }
+    return most;
   }
   if (op == CD_OP_LANCZOS) return cd::lanczos_workspace_bytes(n, n_patches);
   return cd::relax_workspace_bytes(op, n, n_patches, total_active, precision);
 }
 
-static int check_ws(int op, int64_t n, int precision, void* ws, size_t ws_bytes, Plan& P) {
+static int check_ws(int op, int64_t n, int precision, void* ws, size_t ws_bytes, Plan& P,
+                    int shape = -1) {
   if (!ws) return CD_ERR_WORKSPACE;
-  if (!make_plan(op, n, precision, nullptr, P)) return CD_ERR_INVALID_ARG;
+  if (shape < 0 && precision == CD_MIXED) shape = tuned_shape(op, n);
+  if (!make_plan(op, n, precision, nullptr, P, shape)) return CD_ERR_INVALID_ARG;
   if (ws_bytes < P.total) return CD_ERR_WORKSPACE;
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
-  make_plan(op, n, precision, base, P);
+  make_plan(op, n, precision, base, P, shape);
   return CD_OK;
 }
 
-int coulomb_energy(const double* x, const double* y, int64_t n, int precision, double* e_total,
-                   double* e_local, void* ws, size_t ws_bytes, void* stream) {
+static int energy_impl(const double* x, const double* y, int64_t n, int precision,
+                       double* e_total, double* e_local, void* ws, size_t ws_bytes,
+                       hipStream_t st, int shape) {
   if (!x || !y || !e_total) return CD_ERR_INVALID_ARG;
   Plan P;
-  int rc = check_ws(CD_OP_ENERGY, n, precision, ws, ws_bytes, P);
+  int rc = check_ws(CD_OP_ENERGY, n, precision, ws, ws_bytes, P, shape);
   if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
   if (precision == CD_MIXED) {
     if (e_local) run_sym<kEnergy, true>(P, st, e_local, nullptr, e_total);
@@ -1189,13 +1232,13 @@ int coulomb_energy(const double* x, const double* y, int64_t n, int precision, d
   return hip_status(hipGetLastError());
 }
 
-int coulomb_forces(const double* x, const double* y, int64_t n, int precision, double* fx,
-                   double* fy, double* e_total, void* ws, size_t ws_bytes, void* stream) {
+static int forces_impl(const double* x, const double* y, int64_t n, int precision, double* fx,
+                       double* fy, double* e_total, void* ws, size_t ws_bytes, hipStream_t st,
+                       int shape) {
   if (!x || !y || !fx || !fy) return CD_ERR_INVALID_ARG;
   Plan P;
-  int rc = check_ws(CD_OP_FORCES, n, precision, ws, ws_bytes, P);
+  int rc = check_ws(CD_OP_FORCES, n, precision, ws, ws_bytes, P, shape);
   if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
   if (precision == CD_MIXED) {
     run_sym<kForces, false>(P, st, fx, fy, e_total);
@@ -1206,17 +1249,86 @@ int coulomb_forces(const double* x, const double* y, int64_t n, int precision, d
   return hip_status(hipGetLastError());
 }
 
-int coulomb_hvp(const double* x, const double* y, const double* vx, const double* vy, int64_t n,
-                int precision, double* hx, double* hy, void* ws, size_t ws_bytes, void* stream) {
+static int hvp_impl(const double* x, const double* y, const double* vx, const double* vy,
+                    int64_t n, int precision, double* hx, double* hy, void* ws, size_t ws_bytes,
+                    hipStream_t st, int shape) {
   if (!x || !y || !vx || !vy || !hx || !hy) return CD_ERR_INVALID_ARG;
   Plan P;
-  int rc = check_ws(CD_OP_HVP, n, precision, ws, ws_bytes, P);
+  int rc = check_ws(CD_OP_HVP, n, precision, ws, ws_bytes, P, shape);
   if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
   if ((rc = stage(P, x, y, vx, vy, st))) return rc;
   if (precision == CD_MIXED) run_sym<kHvp, false>(P, st, hx, hy, nullptr);
   else run_one64<kHvp>(P, st, hx, hy);
   return hip_status(hipGetLastError());
+}
+
+int coulomb_energy(const double* x, const double* y, int64_t n, int precision, double* e_total,
+                   double* e_local, void* ws, size_t ws_bytes, void* stream) {
+  return energy_impl(x, y, n, precision, e_total, e_local, ws, ws_bytes, (hipStream_t)stream,
+                     -1);
+}
+
+int coulomb_forces(const double* x, const double* y, int64_t n, int precision, double* fx,
+                   double* fy, double* e_total, void* ws, size_t ws_bytes, void* stream) {
+  return forces_impl(x, y, n, precision, fx, fy, e_total, ws, ws_bytes, (hipStream_t)stream, -1);
+}
+
+int coulomb_hvp(const double* x, const double* y, const double* vx, const double* vy, int64_t n,
+                int precision, double* hx, double* hy, void* ws, size_t ws_bytes, void* stream) {
+  return hvp_impl(x, y, vx, vy, n, precision, hx, hy, ws, ws_bytes, (hipStream_t)stream, -1);
+}
+
+int coulomb_autotune(const double* x, const double* y, int64_t n, int op, void* ws,
+                     size_t ws_bytes, void* stream, int32_t* shape_out) {
+  if (!x || !y || !shape_out) return CD_ERR_INVALID_ARG;
+  if (op != CD_OP_ENERGY && op != CD_OP_FORCES && op != CD_OP_HVP) return CD_ERR_INVALID_ARG;
+  const size_t need = coulomb_workspace_bytes(op, n, 0, 0, CD_MIXED);
+  if (!need) return CD_ERR_INVALID_ARG;
+  if (!ws) return CD_ERR_WORKSPACE;
+  const size_t outb = ((size_t)n * 2 * sizeof(double) + 8 + 255) & ~size_t(255);
+  if (ws_bytes < need + outb + 256) return CD_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  // outputs at the aligned start, the operation's scratch after them
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  double* o0 = reinterpret_cast<double*>(base);
+  double* o1 = o0 + n;
+  double* oe = o1 + n;
+  char* rws = base + outb;
+  const size_t rbytes = ws_bytes - (size_t)(rws - reinterpret_cast<char*>(ws));
+  auto run = [&](int sh) {
+    if (op == CD_OP_ENERGY) return energy_impl(x, y, n, CD_MIXED, oe, nullptr, rws, rbytes, st, sh);
+    if (op == CD_OP_FORCES) return forces_impl(x, y, n, CD_MIXED, o0, o1, oe, rws, rbytes, st, sh);
+    return hvp_impl(x, y, x, y, n, CD_MIXED, o0, o1, rws, rbytes, st, sh);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_status(hipEventCreate(&e0));
+  if (!rc) rc = hip_status(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
+    if ((rc = run(sh))) break;  // warm-up
+    if ((rc = hip_status(hipEventRecord(e0, st)))) break;
+    for (int k = 0; k < 3 && !rc; ++k) rc = run(sh);
+    if (rc || (rc = hip_status(hipEventRecord(e1, st)))) break;
+    if ((rc = hip_status(hipEventSynchronize(e1)))) break;
+    float ms = 0.f;
+    if ((rc = hip_status(hipEventElapsedTime(&ms, e0, e1)))) break;
+    if (sh == 0 || ms < best_ms) {
+      best = sh;
+      best_ms = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(current_device(), op, n)] = best;
+  }
+  shape_out[0] = best;
+  shape_out[1] = kShapes[best].W;
+  shape_out[2] = kShapes[best].L;
+  return CD_OK;
 }
 
 int coulomb_validate(const double* x, const double* y, int64_t n, int32_t* flags_out,

@@ -38,6 +38,7 @@ constexpr int kSymBatchMax = 1024;
 struct Plan {
   int n = 0, npad = 0, nb = 0;
   int ns = 0;                              // super-blocks (symmetric pass)
+  int shape = 0;                           // symmetric pass launch shape (index)
   int W = 0, L = 0, C = 0, G = 0, S = 0;  // symmetric pass
   int Cb = 0, mj = 0;                     // chunks per batch, j slots per chunk
   int splits = 0, jb = 0;                 // one-sided pass
@@ -57,7 +58,9 @@ struct Plan {
 };
 
 
-bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P);
+// shape: index into the symmetric pass's list of launch shapes (out of
+// range: the default); the entry points pass the one coulomb_autotune chose.
+bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape = -1);
 int stage(const Plan& P, const double* x, const double* y, const double* vx, const double* vy,
           hipStream_t st);
 

@@ -136,6 +136,29 @@ def hvp(x, y, vx, vy, precision: int = MIXED):
     return hx, hy
 
 
+def autotune(x, y, op: int = OP_FORCES):
+    """Time the mixed pair pass's launch shapes for `op` (OP_ENERGY,
+    OP_FORCES or OP_HVP) on these positions and keep the fastest for later
+    calls with the same op and n on this device.  Returns (index, waves,
+    offsets per chunk)."""
+    dev = _chk(x, y)
+    n = x.numel()
+    L = lib()
+    if not getattr(L, "_tune_bound", False):
+        L.coulomb_autotune.restype = ctypes.c_int
+        L.coulomb_autotune.argtypes = [_vp, _vp, _i64, ctypes.c_int, _vp, _sz, _vp, _vp]
+        L._tune_bound = True
+    nb = int(L.coulomb_workspace_bytes(op, n, 0, 0, MIXED))
+    if nb == 0:
+        raise CoulombError(f"invalid sizes for op {op}: n={n}")
+    nb += 16 * n + 512
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = (ctypes.c_int32 * 3)()
+    check(L.coulomb_autotune(x.data_ptr(), y.data_ptr(), n, int(op), ws.data_ptr(), nb, stream_ptr(dev),
+                             ctypes.cast(out, _vp)), "coulomb_autotune")
+    return int(out[0]), int(out[1]), int(out[2])
+
+
 def validate(x, y):
     """Per-charge domain flags (CD_FLAG_* bits) and the flagged count."""
     dev = _chk(x, y)

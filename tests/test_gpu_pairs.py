@@ -155,6 +155,28 @@ def test_mixed_large_n_batched(dev):
     assert errE <= tol["E"] and euler <= 10 * tol["F"]
 
 
+def test_autotune_then_parity(dev):
+    # the tuner picks one of the launch shapes; calls after it use that shape,
+    # stay deterministic and keep parity with the oracle
+    x, y = W.warped_lattice(30000, 0.02, 31)
+    n = x.size
+    xt, yt = t(x, dev), t(y, dev)
+    idx, waves, offs = ops.autotune(xt, yt, ops.OP_FORCES)
+    print(f"[tune] n={n} shape={idx} waves={waves} offsets={offs}", flush=True)
+    assert 0 <= idx and waves in (2, 4, 8) and offs >= 1
+    a = ops.forces(xt, yt, MIXED)
+    b = ops.forces(xt, yt, MIXED)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    rows = np.sort(np.random.default_rng(5).choice(n, 256, replace=False)).astype(np.int32)
+    ofx, ofy, _ = O.rows(x, y, rows)
+    fx, fy = a[0].cpu().numpy(), a[1].cpu().numpy()
+    assert rel_rms(fx[rows], fy[rows], ofx, ofy) <= TOL[MIXED]["F"]
+    E0 = O.energy(x, y)
+    assert abs(a[2].item() - E0) / E0 <= TOL[MIXED]["E"]
+
+
 def test_validate_flags(dev):
     x, y = W.uniform_disk(300, 9)
     x[3], y[3] = np.nan, 0.0
