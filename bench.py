@@ -15,8 +15,10 @@ Printed: one JSON line with the driver's fields plus
 
   relax         the batched subdomain relax of 256 patches (sizes U{200..5000})
                 on the same configuration, mixed path, seconds per batch ("cycle");
-                and mixed vs plain FP64 on the first 64 of those patches with the
-                per-patch energy agreement (same minimum: E_sub to 1e-12).
+                mixed vs plain FP64 on the first 64 of those patches with the
+                per-patch energy agreement (same minimum: E_sub to 1e-12), an
+                ablation (the mixed path's model with FP64 pairs only), and both
+                paths from common near-minimum starts (same basin, equal E).
 
 Other modes: --cycles K runs K perturb-and-relax cycles (64 kicked patches
 each, greedy commit) and prints energy versus wall time; --relax-only mixed|fp64
@@ -29,6 +31,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extr
 """
 import argparse
 import ctypes
+import statistics
 import json
 import os
 import sys
@@ -66,17 +69,17 @@ def timed(fn, steps, warmup, lib, hip):
         hip.hipEventCreate(ctypes.byref(a))
         hip.hipEventCreate(ctypes.byref(b))
         evs.append((a, b))
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    t0.record()
-    for a, b in evs:
+    marks[0].record()
+    for k, (a, b) in enumerate(evs):
         lib.coulomb_set_kernel_events(a, b)
         fn()
-    t1.record()
+        marks[k + 1].record()
     torch.cuda.synchronize()
     lib.coulomb_set_kernel_events(None, None)
-    region_ms = t0.elapsed_time(t1) / steps
+    region_ms = marks[0].elapsed_time(marks[-1]) / steps
+    calls = [marks[k].elapsed_time(marks[k + 1]) for k in range(steps)]
     ks = []
     for a, b in evs:
         ms = ctypes.c_float()
@@ -84,6 +87,8 @@ def timed(fn, steps, warmup, lib, hip):
         ks.append(ms.value)
         hip.hipEventDestroy(a)
         hip.hipEventDestroy(b)
+    timed.last = {"call_ms_median": statistics.median(calls), "call_ms_min": min(calls),
+                  "kernel_ms_median": statistics.median(ks), "kernel_ms_min": min(ks)}
     return region_ms, sum(ks) / len(ks)
 
 
@@ -102,11 +107,30 @@ def cpu_baseline(x, y, seconds=15.0):
         rows_done += block.size
         k += 1
     dt = time.perf_counter() - t
-    return {"value": rows_done * (n - 1) / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
+    cores = O.num_threads()
+    # the same sums on one thread, over a smaller sample (about a fifth of the time)
+    O.set_threads(1)
+    r1 = 0
+    t1 = time.perf_counter()
+    k1 = 0
+    while time.perf_counter() - t1 < seconds / 5:
+        O.rows(x, y, (block[: max(1, block.size // 8)] + k1) % n)
+        r1 += max(1, block.size // 8)
+        k1 += 1
+    d1 = time.perf_counter() - t1
+    O.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": rows_done * (n - 1) / dt, "unit": "pair-interactions/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{rows_done} rows (blocks of {block.size} evenly spread charges) of the N={n} input, "
                       f"each against all {n - 1} others: FP64 Neumaier sums of 1/r and (r_i - r_j)/r^3, "
-                      f"{dt:.1f} s on {O.num_threads()} threads"}
+                      f"{dt:.1f} s on {cores} threads",
+            "value_1_thread": r1 * (n - 1) / d1, "cpu_model": model}
 
 
 def relax_comparison(xt, yt, subset):
@@ -152,6 +176,12 @@ def relax_comparison(xt, yt, subset):
 
     tb_mix, rb_mix = run_from(MIXED)
     tb_fp, rb_fp = run_from(FP64)
+    # ablation: the mixed path's model with FP64 pairs throughout (no FP32 stage)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r_abl = R.relax_subdomains(xt, yt, ps, ids, precision=MIXED, gtol=1e-3, inner_tol=1e300)
+    torch.cuda.synchronize()
+    t_abl = time.perf_counter() - t
     ebm, ebf = rb_mix.e_sub.cpu().numpy(), rb_fp.e_sub.cpu().numpy()
     dbx = np.array([np.hypot(rb_mix.x.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.x.cpu().numpy()[ps[p]:ps[p + 1]],
                              rb_mix.y.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.y.cpu().numpy()[ps[p]:ps[p + 1]]).max()
@@ -183,6 +213,8 @@ def relax_comparison(xt, yt, subset):
         "all_patches_median_rel_energy_diff": float(np.median(rel)),
         "mean_dE_mixed": float(r_mix.dE.mean().item()),
         "mean_dE_fp64": float(r_fp.dE.mean().item()),
+        "ablation_fp64_model_s": t_abl,
+        "ablation_status": st(r_abl),
         "same_basin": {
             "start": "the plain path's endpoints of the subset, kicked by N(0, (0.02 h)^2) per coordinate",
             "mixed_s": tb_mix, "fp64_s": tb_fp, "speedup": tb_fp / tb_mix,
@@ -317,6 +349,7 @@ def main():
     shape = ops.autotune(xt, yt, ops.OP_FORCES) if args.tune else (0, 8, 12)
 
     step_ms, kern_ms = timed(lambda: ops.forces(xt, yt, MIXED), args.steps, args.warmup, lib, hip)
+    spread = dict(timed.last)
     value = pairs / (step_ms * 1e-3)
     achieved = FLOPS_EF * pairs / (kern_ms * 1e-3) / 1e12
     out = {
@@ -352,6 +385,7 @@ def main():
             "traffic": traffic_from_profiles(),
             "kernel": "cd::k_sym<1,false> (energy+forces)",
             "kernel_ms": kern_ms,
+            "timing_spread": spread,
             "flops_per_pair": FLOPS_EF,
         },
     }

@@ -82,7 +82,8 @@ int coulomb_forces(const double* x, const double* y, int64_t n, int precision, d
 
 /* Hessian-vector product of Eq. 2's energy: (H v)_i = sum_{j!=i} K(d_ij)
  * (v_i - v_j), K(d) = (3 d d^T - |d|^2 I)/|d|^5, d_ij = r_i - r_j.
- * vx, vy, hx, hy: [n]. */
+ * vx, vy, hx, hy: [n].  CD_MIXED: components of v must stay below 1e8 in
+ * magnitude (padding charges sit at x ~ 1e30 and d.v is formed in FP32). */
 int coulomb_hvp(const double* x, const double* y, const double* vx, const double* vy,
                 int64_t n, int precision, double* hx, double* hy, void* ws, size_t ws_bytes,
                 void* stream);
