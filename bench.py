@@ -26,7 +26,7 @@ times one relax call on the 256 patches of workload 4; --copy-probe runs a
 plain device copy of known size (to calibrate HBM byte counters).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
-                       [--no-relax] [--tune] [--cycles K --cycle-n N]
+                       [--no-relax] [--tune] [--cycles K --cycle-n N --cycle-precision P]
                        [--relax-only mixed|fp64] [--copy-probe]
 """
 import argparse
@@ -263,7 +263,7 @@ def copy_probe(dev):
                       "copy_probe_bytes_written_per_launch": a.numel() * 8}), flush=True)
 
 
-def cycles_mode(dev, cycles, n):
+def cycles_mode(dev, cycles, n, precision):
     import torch
     from paper_2609_24722_amd import workloads as W
     from paper_2609_24722_amd.cycle import perturb_relax_cycles
@@ -271,9 +271,10 @@ def cycles_mode(dev, cycles, n):
     xt = torch.tensor(x, device=dev)
     yt = torch.tensor(y, device=dev)
     log = lambda r: print(json.dumps(r), flush=True)
-    recs = perturb_relax_cycles(xt, yt, cycles, log=log)
+    recs = perturb_relax_cycles(xt, yt, cycles, precision=precision, log=log)
     drift = max(abs(r["energy"] - r["tracked_energy"]) / r["energy"] for r in recs)
-    print(json.dumps({"cycles": cycles, "n": n, "final_energy": recs[-1]["energy"],
+    print(json.dumps({"cycles": cycles, "n": n, "precision": "mixed" if precision else "fp64",
+                      "final_energy": recs[-1]["energy"],
                       "seconds_per_cycle": recs[-1]["wall_s"] / cycles, "max_tracked_drift_rel": drift}),
           flush=True)
 
@@ -307,6 +308,7 @@ def main():
     ap.add_argument("--relax-subset", type=int, default=64)
     ap.add_argument("--cycles", type=int, default=0)
     ap.add_argument("--cycle-n", type=int, default=40000)
+    ap.add_argument("--cycle-precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="pick the pair pass's launch shape with coulomb_autotune before timing")
@@ -326,7 +328,7 @@ def main():
         copy_probe(dev)
         return
     if args.cycles > 0:
-        cycles_mode(dev, args.cycles, args.cycle_n)
+        cycles_mode(dev, args.cycles, args.cycle_n, MIXED if args.cycle_precision == "mixed" else FP64)
         return
     if args.relax_only:
         relax_only(dev, MIXED if args.relax_only == "mixed" else FP64)
@@ -346,7 +348,7 @@ def main():
     vyt = torch.tensor(vy, device=dev)
     torch.cuda.synchronize()
     # launch shape of the pair pass: the library default, or the tuner's pick
-    shape = ops.autotune(xt, yt, ops.OP_FORCES) if args.tune else (0, 8, 12)
+    shape = ops.autotune(xt, yt, ops.OP_FORCES) if args.tune else (0, 8, 8)
 
     step_ms, kern_ms = timed(lambda: ops.forces(xt, yt, MIXED), args.steps, args.warmup, lib, hip)
     spread = dict(timed.last)

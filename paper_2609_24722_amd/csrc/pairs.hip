@@ -467,8 +467,7 @@ __global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(
   __shared__ double ered[16];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // chunk-major dispatch: chunk 0 (which also does the super-diagonals)
-  // starts first, the last chunk (possibly short) ends the grid
+  // chunk-major dispatch: the last chunk (possibly short) ends the grid
   int bid = blockIdx.x;
   if (a.c0 == 0) {
     // first launch: workgroups 0..ns-1 do the pairs inside super-block bid,
@@ -897,15 +896,18 @@ __global__ void k_validate(const double* __restrict__ xs, const double* __restri
 
 // ------------------------------------------------------------------ shapes --
 // Launch shapes of the symmetric pass (waves per workgroup W, offsets per
-// chunk L) that coulomb_autotune chooses from; the first is the default.  All
-// fit the kernel's launch bound (W <= kSymWaves) and the 64 KiB j window.
+// chunk L) that coulomb_autotune chooses from; the first is the default.
+// make_plan clamps each to the kernel's launch bound (W <= kSymWaves) and to
+// the 64 KiB j window.
 struct SymShape {
   int W, L;
 };
-constexpr SymShape kShapes[] = {{8, 12}, {8, 6},  {8, 8},  {8, 16}, {8, 20},
-                                {4, 8},  {4, 12}, {4, 16}, {4, 24}, {2, 24}};
+constexpr SymShape kShapes[] = {{kSymWaves, kSymChunk}, {8, 6}, {8, 12}, {8, 16}, {8, 20},
+                                {4, 8}, {4, 12}, {4, 16}, {4, 24}, {2, 24}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-static_assert(kShapes[0].W == kSymWaves && kShapes[0].L == kSymChunk, "default shape");
+// offsets per chunk that keep the j window (S = W + L - 1 super-blocks of
+// NI KiB each, forces and HVP) within 64 KiB
+constexpr int max_chunk(int W) { return 64 / NI - W + 1; }
 
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int64_t>, int> g_tuned;  // (device, op, n) -> shape
@@ -941,9 +943,10 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shap
     if (shape < 0 || shape >= kNumShapes) shape = 0;
     const SymShape sh = kShapes[shape];
     P.shape = shape;
-    P.W = P.ns < sh.W ? P.ns : sh.W;
-    const int l = P.ns + 1 - P.W;
-    P.L = l < 1 ? 1 : (l > sh.L ? sh.L : l);
+    const int w = sh.W < kSymWaves ? sh.W : kSymWaves;  // the kernel's launch bound
+    P.W = P.ns < w ? P.ns : w;
+    const int l = P.ns + 1 - P.W, lmax = sh.L < max_chunk(w) ? sh.L : max_chunk(w);
+    P.L = l < 1 ? 1 : (l > lmax ? lmax : l);
     const int hmax = P.ns / 2;
     P.C = hmax > 0 ? (hmax + P.L - 1) / P.L : 1;
     P.G = (P.ns + P.W - 1) / P.W;

@@ -17,7 +17,7 @@ namespace cd {
 #define CD_SYM_WAVES 8
 #endif
 #ifndef CD_SYM_CHUNK
-#define CD_SYM_CHUNK 12
+#define CD_SYM_CHUNK 8
 #endif
 #ifndef CD_SYM_WPS
 #define CD_SYM_WPS 8

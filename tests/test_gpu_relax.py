@@ -112,6 +112,40 @@ def test_same_basin_energy_parity(dev):
             assert d <= 1e-3 * h
 
 
+def test_large_patch_same_basin(dev):
+    # a patch of 4500 actives (above the update kernel's register capacity of
+    # 4096, so its two-loop runs through memory) beside a small one: from a
+    # common near-minimum start both paths reach the same minimum
+    n = 20000
+    x, y = W.warped_lattice(n, 0.05, 21)
+    h = W.spacing(n)
+    centres = np.array([17, 15000], dtype=np.int32)
+    sizes = np.array([4500, 300], dtype=np.int32)
+    xt, yt = t(x, dev), t(y, dev)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    idx_np = idx.cpu().numpy()
+    print("[case] large patch same basin", flush=True)
+    base = R.relax_subdomains(xt, yt, ptr, idx, precision=FP64, gtol=1e-4)
+    rng = np.random.default_rng(22)
+    sx = base.x.cpu().numpy() + rng.normal(0, 1e-3 * h, idx_np.size)
+    sy = base.y.cpu().numpy() + rng.normal(0, 1e-3 * h, idx_np.size)
+    rr = np.hypot(sx, sy)
+    sx, sy = np.where(rr > 1, sx / rr, sx), np.where(rr > 1, sy / rr, sy)
+    res = {prec: R.relax_subdomains(xt, yt, ptr, idx, t(sx, dev), t(sy, dev), precision=prec, gtol=1e-4)
+           for prec in (FP64, MIXED)}
+    torch.cuda.synchronize()
+    for prec in (FP64, MIXED):
+        check_endpoints(x, y, ptr, idx_np, res[prec], 1e-4, f"large-{prec}")
+    e64, e32 = res[FP64].e_sub.cpu().numpy(), res[MIXED].e_sub.cpu().numpy()
+    for p in range(ptr.size - 1):
+        sl = slice(ptr[p], ptr[p + 1])
+        d = np.hypot(res[FP64].x.cpu().numpy()[sl] - res[MIXED].x.cpu().numpy()[sl],
+                     res[FP64].y.cpu().numpy()[sl] - res[MIXED].y.cpu().numpy()[sl]).max()
+        print(f"[large] p{p} n={sizes[p]} plain={e64[p]:.15e} mixed={e32[p]:.15e} disp={d / h:.1e} h")
+        assert abs(e32[p] - e64[p]) <= 1e-12 * abs(e64[p])
+        assert d <= 1e-3 * h
+
+
 def test_full_disk_relax_workload1(dev):
     # workload 1: 1000 uniform charges, one patch holding every charge, plain
     # FP64 projected L-BFGS to an inf-norm reduced gradient of 1e-10
