@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle as O
-from paper_2609_24722_amd import FP64, MIXED, workloads as W
+from paper_2609_24722_amd import FP64, MIXED, ops, workloads as W
 from paper_2609_24722_amd import relax as R
 
 pytestmark = pytest.mark.gpu
@@ -171,6 +171,36 @@ def test_full_disk_relax_workload1(dev):
     assert abs(E - res.e_sub.item()) <= 1e-13 * E
     Ea = np.pi / 4 * n ** 2 - 1.5628 * n ** 1.5 + 1.0302 * n - 0.9899 * n ** 0.5 + 4.9255
     assert 0.0 <= (E - Ea) / Ea <= 2e-3
+
+
+def test_full_disk_relax_workload2_certified(dev):
+    # workload 2: the warped lattice of 10 000 charges (sigma 0.1 h), one patch
+    # holding every charge, plain FP64 relax to an inf-norm reduced gradient of
+    # 1e-8 (config 2 states no tolerance; this reading is 1e-8), then the
+    # Lanczos certificate on the tangent space: the smallest Ritz value is
+    # positive and its residual below half of it
+    x, y = W.workload(2)
+    n = x.size
+    xt, yt = t(x, dev), t(y, dev)
+    ptr = np.array([0, n], dtype=np.int32)
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    print("[case] full disk n=10000 + certificate", flush=True)
+    res = R.relax_subdomains(xt, yt, ptr, idx, precision=FP64, gtol=1e-8, max_iter=50000)
+    torch.cuda.synchronize()
+    print(f"[full2] status={res.status.item()} gtan={res.gtan_inf.item():.3e} iters={res.iters.cpu().numpy()}")
+    assert res.status.item() == 0 and res.gtan_inf.item() <= 1e-8
+    xo, yo = res.x.cpu().numpy(), res.y.cpu().numpy()
+    fx, fy = O.forces(xo, yo)
+    _, _, held, m = O.reduce_grad(xo, yo, -fx, -fy)
+    assert m <= 2e-8
+    assert np.all((fx * xo + fy * yo)[held == 1] > 0)
+    E = O.energy(xo, yo)
+    assert abs(E - res.e_sub.item()) <= 1e-13 * E
+    Ea = np.pi / 4 * n ** 2 - 1.5628 * n ** 1.5 + 1.0302 * n - 0.9899 * n ** 0.5 + 4.9255
+    assert 0.0 <= (E - Ea) / Ea <= 2e-3
+    c = ops.tangent_lanczos(res.x.contiguous(), res.y.contiguous(), k=4000)
+    print(f"[full2] lanczos {c}")
+    assert c["certified"] and c["theta_min"] > 0 and c["resid"] < 0.5 * c["theta_min"]
 
 
 def test_kicked_patches_workload5_small(dev):
