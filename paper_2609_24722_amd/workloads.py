@@ -21,6 +21,9 @@ Sec. II.E: subdomains of a few hundred to a few thousand active charges):
   and sizes (uniform integers); the k-nearest selection itself is part of the
   method and is not done here.
 * ``kicks``          -- Gaussian displacements of the active charges.
+* ``zone_draws``     -- the random numbers of a cycle's zone choices: per zone
+  (u, v, px, py), u and v uniform in [0, 1), (px, py) uniform in the open
+  unit disk by the same rejection rule as ``uniform_disk``.
 
 Seeds follow one rule: workload k uses 1000 + k, its secondary draws 1100 + k.
 """
@@ -103,6 +106,18 @@ def kicks(total_active: int, sigma_abs: float, seed: int):
     rng = np.random.default_rng(seed)
     k = rng.normal(0.0, sigma_abs, size=(total_active, 2))
     return np.ascontiguousarray(k[:, 0]), np.ascontiguousarray(k[:, 1])
+
+
+def zone_draws(n_zones: int, seed: int) -> np.ndarray:
+    """Flat float64 array [4 * n_zones] of (u, v, px, py) per zone."""
+    rng = np.random.default_rng(seed)
+    uv = rng.uniform(0.0, 1.0, size=(n_zones, 2))
+    px, py = uniform_disk(n_zones, seed + 1) if n_zones > 0 else (np.zeros(0), np.zeros(0))
+    out = np.empty((n_zones, 4))
+    out[:, 0:2] = uv
+    out[:, 2] = px
+    out[:, 3] = py
+    return np.ascontiguousarray(out.ravel())
 
 
 # The five workloads, by number.  Sizes are the paper's (Sec. II.A, II.E).
