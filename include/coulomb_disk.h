@@ -45,7 +45,8 @@ enum {
   CD_ERR_INVALID_ARG = -1,
   CD_ERR_WORKSPACE = -2,
   CD_ERR_HIP = -3,
-  CD_ERR_DOMAIN = -4
+  CD_ERR_DOMAIN = -4,
+  CD_ERR_CAPACITY = -5
 };
 
 /* operation selectors for coulomb_workspace_bytes */
@@ -56,7 +57,9 @@ enum {
   CD_OP_VALIDATE = 3,
   CD_OP_PATCHES = 4,
   CD_OP_RELAX = 5,
-  CD_OP_LANCZOS = 6
+  CD_OP_LANCZOS = 6,
+  CD_OP_DEFECT = 7,
+  CD_OP_ZONES = 8
 };
 
 /* Per-charge flags written by coulomb_validate. */
@@ -64,7 +67,8 @@ enum { CD_FLAG_NONFINITE = 1, CD_FLAG_OUTSIDE = 2, CD_FLAG_COINCIDENT = 4 };
 
 /* Bytes of device scratch that `op` needs for these sizes (n_patches and
  * total_active matter only for CD_OP_PATCHES / CD_OP_RELAX; lanczos_k is
- * passed in n_patches for CD_OP_LANCZOS).  Returns 0 for invalid sizes. */
+ * passed in n_patches for CD_OP_LANCZOS; the number of zones in n_patches
+ * for CD_OP_ZONES).  Returns 0 for invalid sizes. */
 size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total_active,
                                int precision);
 
@@ -169,6 +173,75 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                      double* x_out, double* y_out, double* dE, double* e_sub,
                      double* gtan_inf, int32_t* iters, int32_t* status, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* Defect-targeted zones of a subdomain cycle (Sec. II.C).  Options (host
+ * struct) of defect_zones. */
+typedef struct {
+  double kappa;    /* threshold mu + kappa * sigma_e of step 2 (the printed
+                      rule is kappa = -1; +1 flags a high-energy tail) */
+  double p_defect; /* probability that a centre is a defect charge (step 3: 0.8) */
+  double r_lo;     /* zone radius range of the oscillation, 0 <= r_lo <= r_hi */
+  double r_hi;
+  int64_t t0;      /* index of the first zone of this call in the cycle, >= 0 */
+  int32_t period;  /* zones per period of the radius oscillation, >= 1 */
+  int32_t reserved;
+} cd_zone_opts;
+
+/* Steps 2-3 of Sec. II.C and the zone radius.  From the local energies
+ * e[n] (device; the e_local of coulomb_energy is step 1):
+ *   mu = (1/n) sum e_i and sigma_e = sqrt((1/n) sum (e_i - mu)^2) (FP64, fixed
+ *   summation order), thr = mu + kappa * sigma_e, and the defect list
+ *   D = {i : e_i > thr} in increasing index order (empty when e is constant
+ *   or not finite).
+ * Then for each zone t = 0..n_zones-1, from the caller's uniform draws
+ * (device double [4 n_zones]: u, v in [0, 1) and a point (px, py) drawn
+ * uniformly in the disk, per zone):
+ *   centre: if u < p_defect and |D| > 0, the position of charge
+ *     D[min(floor(v |D|), |D| - 1)], and centre_idx[t] = that charge;
+ *     otherwise (px, py), and centre_idx[t] = -1.
+ *   radius: s = (t0 + t) mod period, tri = 2 min(s, period - s) / period,
+ *     rz[t] = r_lo + (r_hi - r_lo) * tri (a triangle wave), each operation
+ *     rounded once in FP64.
+ * cx, cy, rz: device double [n_zones]; centre_idx: device int32 [n_zones]
+ * (all may be NULL when n_zones = 0: statistics only).  stats (nullable):
+ * device double [4] = mu, sigma_e, thr, |D|.  defect_idx (nullable): device
+ * int32 [n], its first |D| entries receive D.  ws: at least
+ * coulomb_workspace_bytes(CD_OP_DEFECT, n, 0, 0, 0) bytes.  Does not
+ * synchronise. */
+int defect_zones(const double* x, const double* y, const double* e, int64_t n, int32_t n_zones,
+                 const double* draws, const cd_zone_opts* opts, double* cx, double* cy,
+                 double* rz, int32_t* centre_idx, double* stats, int32_t* defect_idx, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Active sets of zones (Sec. II.C step 4): zone p holds every charge j with
+ * (dx*dx) + (dy*dy) <= rz[p]*rz[p], dx = x[j] - cx[p], dy = y[j] - cy[p], each
+ * operation rounded once in FP64, listed in increasing index order.
+ * cx, cy, rz: device double [n_zones].  patch_ptr: host int32 [n_zones + 1],
+ * filled with the offsets (patch_ptr[0] = 0) in every case that returns
+ * CD_OK or CD_ERR_CAPACITY.  active_idx: device int32 [capacity]; if the
+ * zones hold more than capacity entries in total, nothing is written and
+ * CD_ERR_CAPACITY is returned (call again with patch_ptr[n_zones] entries).
+ * Zones may be empty or overlap.  ws: at least
+ * coulomb_workspace_bytes(CD_OP_ZONES, n, n_zones, 0, 0) bytes.
+ * Synchronises the stream. */
+int zone_patches(const double* x, const double* y, int64_t n, int32_t n_zones, const double* cx,
+                 const double* cy, const double* rz, int32_t* patch_ptr, int32_t* active_idx,
+                 int64_t capacity, void* ws, size_t ws_bytes, void* stream);
+
+/* Batches of a cycle's zones for side-by-side relaxation (host code; all
+ * pointers host).  Zones a and b conflict when (cx_a - cx_b)^2 +
+ * (cy_a - cy_b)^2 < (rz_a + rz_b + gap)^2 (each operation rounded once in
+ * FP64); no two zones of one batch conflict and no batch holds more than
+ * cap zones.  Zones are placed in sequence order:
+ *   keep_order != 0: zone t goes to the first batch after those of every
+ *     earlier zone it conflicts with (conflicting zones keep their order);
+ *   keep_order == 0: zone t goes to the first batch that holds no zone it
+ *     conflicts with (first fit: fewer, fuller batches).
+ * In both cases batches that are full are passed over.  batch: int32
+ * [n_zones]; n_batches (nullable): int32 [1]. */
+int zone_batches(const double* cx, const double* cy, const double* rz, int32_t n_zones,
+                 double gap, int32_t cap, int32_t keep_order, int32_t* batch,
+                 int32_t* n_batches);
 
 /* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
  * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE

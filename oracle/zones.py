@@ -18,9 +18,10 @@ zone radius):
   drawn uniformly over the disk.
 * ``zones``        -- the active set of each zone: every charge within the
   zone radius of its centre (step 4).
-* ``zone_batches`` -- the order in which a GPU may relax zones side by side:
-  zone t runs after every earlier zone whose disk comes within ``gap`` of
-  its own, batches hold at most ``cap`` zones.
+* ``zone_batches`` -- batches of zones a GPU may relax side by side: no two
+  zones of a batch come within ``gap`` of each other, batches hold at most
+  ``cap`` zones; in sequence order either after every earlier conflicting
+  zone (order kept) or in the first batch free of conflicts (first fit).
 
 Readings where the paper is silent or ambiguous:
 
@@ -116,22 +117,24 @@ def conflict(ax, ay, ar, bx, by, br, gap: float) -> bool:
     return dx * dx + dy * dy < reach * reach
 
 
-def zone_batches(cx, cy, rz, gap: float, cap: int):
-    """Batch index of each zone: the smallest batch after those of all
-    earlier conflicting zones that still holds fewer than cap zones."""
+def zone_batches(cx, cy, rz, gap: float, cap: int, keep_order: bool = True):
+    """Batch index of each zone, zones taken in sequence order.  keep_order:
+    the first batch after those of all earlier conflicting zones; otherwise
+    the first batch holding no zone in conflict with it (first fit).  Either
+    way batches already holding cap zones are passed over."""
     cx = [float(a) for a in cx]
     cy = [float(a) for a in cy]
     rz = [float(a) for a in rz]
     batch = []
-    size = {}
+    members = {}
     for t in range(len(cx)):
-        need = 0
+        clash = set()
         for s in range(t):
             if conflict(cx[s], cy[s], rz[s], cx[t], cy[t], rz[t], gap):
-                need = max(need, batch[s] + 1)
-        b = need
-        while size.get(b, 0) >= cap:
+                clash.add(batch[s])
+        b = (max(clash) + 1 if clash else 0) if keep_order else 0
+        while len(members.get(b, [])) >= cap or (not keep_order and b in clash):
             b += 1
         batch.append(b)
-        size[b] = size.get(b, 0) + 1
+        members.setdefault(b, []).append(t)
     return np.asarray(batch, dtype=np.int32)

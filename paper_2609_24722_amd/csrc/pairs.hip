@@ -1180,6 +1180,7 @@ int hvp64_apply(const Plan& P, const double* vx, const double* vy, double* hx, d
 size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total_active,
                              int precision);
 size_t lanczos_workspace_bytes(int64_t n, int k);
+size_t zones_workspace_bytes(int op, int64_t n, int32_t n_zones);
 
 }  // namespace cd
 
@@ -1203,6 +1204,10 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
     return most;
   }
   if (op == CD_OP_LANCZOS) return cd::lanczos_workspace_bytes(n, n_patches);
+  if (op == CD_OP_DEFECT || op == CD_OP_ZONES) {
+    if (n < 1 || n > (1 << 26) || (op == CD_OP_ZONES && n_patches < 1)) return 0;
+    return cd::zones_workspace_bytes(op, n, n_patches);
+  }
   return cd::relax_workspace_bytes(op, n, n_patches, total_active, precision);
 }
 
@@ -1360,6 +1365,7 @@ const char* coulomb_status_string(int code) {
     case CD_ERR_WORKSPACE: return "workspace missing or too small";
     case CD_ERR_HIP: return "HIP runtime error";
     case CD_ERR_DOMAIN: return "positions outside the domain";
+    case CD_ERR_CAPACITY: return "output capacity too small (sizes reported)";
     default: return "unknown status";
   }
 }

@@ -158,24 +158,33 @@ def test_zone_centres_rule():
     assert int((ci >= 0).sum()) == int((d[0::4] < 0.8).sum())
 
 
-def _check_batches(cx, cy, rz, gap, cap, b):
-    """Defining properties, by brute force: conflicting zones keep their
-    order, batches hold at most cap zones, and each zone sits in the first
-    batch that allows both."""
+def _check_batches(cx, cy, rz, gap, cap, b, keep_order):
+    """Defining properties, by brute force: no batch holds two conflicting
+    zones or more than cap zones; ordered, conflicting zones keep their order
+    and each zone sits in the first batch after its conflicts that had room;
+    first fit, every earlier batch was full or held a conflicting zone."""
     T = len(cx)
     size = {}
+    members = {}
+    hit = lambda s, t: math.hypot(cx[s] - cx[t], cy[s] - cy[t]) < rz[s] + rz[t] + gap - 1e-12
     for t in range(T):
-        need = 0
-        for s in range(t):
-            dx, dy = cx[s] - cx[t], cy[s] - cy[t]
-            if math.hypot(dx, dy) < rz[s] + rz[t] + gap - 1e-12:
-                assert b[s] < b[t]
-                need = max(need, b[s] + 1)
-        assert b[t] >= need
-        for q in range(need, b[t]):  # every earlier admissible batch was full
-            assert size.get(q, 0) >= cap
+        clash = {b[s] for s in range(t) if hit(s, t)}
+        assert b[t] not in clash
+        if keep_order:
+            need = max(clash) + 1 if clash else 0
+            assert b[t] >= need
+            for q in range(need, b[t]):
+                assert size.get(q, 0) >= cap
+        else:
+            for q in range(b[t]):
+                assert size.get(q, 0) >= cap or q in clash
         size[b[t]] = size.get(b[t], 0) + 1
+        members.setdefault(b[t], []).append(t)
     assert max(size.values()) <= cap
+    for zs in members.values():
+        for i in range(len(zs)):
+            for j in range(i):
+                assert not hit(zs[j], zs[i])
 
 
 def test_zone_batches_hand_cases():
@@ -184,22 +193,25 @@ def test_zone_batches_hand_cases():
     cy = [0.0, 0.0, 0.0, 0.0, 0.0]
     rz = [0.1] * 5
     assert Z.zone_batches(cx, cy, rz, 0.0, 10).tolist() == [0, 1, 2, 3, 0]
+    assert Z.zone_batches(cx, cy, rz, 0.0, 10, keep_order=False).tolist() == [0, 1, 0, 1, 0]
     # zones 0.3 apart with radii 0.1: disjoint without a gap, in conflict with gap 0.15
     cx = [0.0, 0.3, 0.6]
     assert Z.zone_batches(cx, [0.0] * 3, [0.1] * 3, 0.0, 10).tolist() == [0, 0, 0]
     assert Z.zone_batches(cx, [0.0] * 3, [0.1] * 3, 0.15, 10).tolist() == [0, 1, 2]
+    assert Z.zone_batches(cx, [0.0] * 3, [0.1] * 3, 0.15, 10, keep_order=False).tolist() == [0, 1, 0]
     # capacity 1: one zone per batch, in order
     assert Z.zone_batches(cx, [0.0] * 3, [0.1] * 3, 0.0, 1).tolist() == [0, 1, 2]
     # capacity 2 with disjoint zones
     assert Z.zone_batches(cx, [0.0] * 3, [0.1] * 3, 0.0, 2).tolist() == [0, 0, 1]
 
 
+@pytest.mark.parametrize("keep_order", [True, False])
 @pytest.mark.parametrize("cap", [4, 1000])
-def test_zone_batches_random_properties(cap):
+def test_zone_batches_random_properties(cap, keep_order):
     rng = np.random.default_rng(11)
     T = 120
     cx = rng.uniform(-1, 1, T)
     cy = rng.uniform(-1, 1, T)
     rz = rng.uniform(0.02, 0.2, T)
-    b = Z.zone_batches(cx, cy, rz, 0.01, cap).tolist()
-    _check_batches(cx.tolist(), cy.tolist(), rz.tolist(), 0.01, cap, b)
+    b = Z.zone_batches(cx, cy, rz, 0.01, cap, keep_order).tolist()
+    _check_batches(cx.tolist(), cy.tolist(), rz.tolist(), 0.01, cap, b, keep_order)
