@@ -19,15 +19,23 @@ Printed: one JSON line with the driver's fields plus
                 per-patch energy agreement (same minimum: E_sub to 1e-12), an
                 ablation (the mixed path's model with FP64 pairs only), and both
                 paths from common near-minimum starts (same basin, equal E).
+  defect_cycle  one defect-targeted cycle of the paper's method (Sec. II.C):
+                T = 1000 zones on fresh positions of the same workload, local
+                energies and defect list, zone centres and oscillating radii,
+                first-fit batches of mutually apart zones, mixed relax and
+                greedy commit; seconds per cycle and the energy it gains.
+                --no-relax skips it with the other relax measurements.
 
 Other modes: --cycles K runs K perturb-and-relax cycles (64 kicked patches
 each, greedy commit) and prints energy versus wall time; --relax-only mixed|fp64
-times one relax call on the 256 patches of workload 4; --copy-probe runs a
-plain device copy of known size (to calibrate HBM byte counters).
+times one relax call on the 256 patches of workload 4; --defect-only mixed|fp64
+runs one defect-targeted cycle; --copy-probe runs a plain device copy of known
+size (to calibrate HBM byte counters).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
                        [--no-relax] [--tune] [--cycles K --cycle-n N --cycle-precision P]
-                       [--relax-only mixed|fp64] [--copy-probe]
+                       [--relax-only mixed|fp64] [--defect-only mixed|fp64 --defect-T T
+                       --defect-kappa K] [--no-defect] [--copy-probe]
 """
 import argparse
 import ctypes
@@ -279,6 +287,28 @@ def cycles_mode(dev, cycles, n, precision):
           flush=True)
 
 
+def defect_cycle_run(dev, n, kappa, precision, T=1000, log=None):
+    """One defect-targeted cycle of T zones (Sec. II.C) on fresh positions of
+    the N-charge lattice; returns its summary without the per-batch list."""
+    import torch
+    from paper_2609_24722_amd import workloads as W
+    from paper_2609_24722_amd.cycle import defect_cycle
+    x, y = W.workload(3, n)
+    xt = torch.tensor(x, device=dev)
+    yt = torch.tensor(y, device=dev)
+    out = defect_cycle(xt, yt, T=T, kappa=kappa, precision=precision, log=log)
+    recs = out.pop("batch_records")
+    out["batch_zones_first_last"] = [recs[0]["zones"], recs[-1]["zones"]] if recs else []
+    out["workload"] = (f"N={n} warped lattice (sigma 0.02 h, seed 1003); T={T} zones, kappa={kappa}, "
+                       f"p_defect 0.8, radius triangle wave (period 250) from sqrt(200/N) to sqrt(4000/N), "
+                       f"first-fit batches of mutually apart zones (gap 2h), relax gtol 1e-3, "
+                       f"{'mixed' if precision else 'fp64'}")
+    out["rel_energy_drop"] = (out["E_start"] - out["E_end"]) / out["E_start"]
+    out["tracked_minus_fresh_rel"] = (out["tracked_energy"] - out["E_end"]) / out["E_end"]
+    out["context_paper_first_cycle_hours_cpu"] = 31
+    return out
+
+
 def traffic_from_profiles():
     """HBM bytes per launch of the pair kernel from the committed counter
     summary, if it matches the current kernel build; else None."""
@@ -312,6 +342,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="pick the pair pass's launch shape with coulomb_autotune before timing")
+    ap.add_argument("--no-defect", action="store_true", help="skip the defect-targeted cycle")
+    ap.add_argument("--defect-only", choices=["mixed", "fp64"], default=None,
+                    help="run one defect-targeted cycle (N=--n, T=--defect-T) and exit")
+    ap.add_argument("--defect-T", type=int, default=1000)
+    ap.add_argument("--defect-kappa", type=float, default=-1.0)
     ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
@@ -332,6 +367,12 @@ def main():
         return
     if args.relax_only:
         relax_only(dev, MIXED if args.relax_only == "mixed" else FP64)
+        return
+    if args.defect_only:
+        log = lambda r: print(json.dumps(r), flush=True)
+        print(json.dumps(defect_cycle_run(dev, args.n, args.defect_kappa,
+                                          MIXED if args.defect_only == "mixed" else FP64,
+                                          args.defect_T, log)), flush=True)
         return
     lib = ops.lib()
     lib.coulomb_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -405,6 +446,8 @@ def main():
         out["extra"] = extra
     if not args.no_relax:
         out["relax"] = relax_comparison(xt, yt, args.relax_subset)
+    if not args.no_relax and not args.no_defect:  # --no-relax skips every relax measurement
+        out["defect_cycle"] = defect_cycle_run(dev, n, args.defect_kappa, MIXED, args.defect_T)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x, y)
     print(json.dumps(out), flush=True)

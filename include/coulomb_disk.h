@@ -139,7 +139,8 @@ typedef struct {
                         against gtol); L-BFGS on the model = explicit active and halo
                         pairs (FP32 while the exact gradient exceeds inner_tol, FP64
                         after) + the expanded far field as a quadratic] */
-  int32_t max_iter;  /* L-BFGS iterations: CD_FP64 in total, CD_MIXED per round */
+  int32_t max_iter;  /* L-BFGS iterations: CD_FP64 in total, CD_MIXED per round;
+                        0 = no iteration: the outputs evaluate the start */
   int32_t lbfgs_m;   /* L-BFGS memory, 1..16 (0 = 8); the workspace is sized for 16 */
   int32_t max_outer; /* CD_MIXED: rounds, each one exact far-field expansion (0 = 40) */
   double gtol;       /* tolerance on the inf-norm of the exact FP64 reduced gradient */

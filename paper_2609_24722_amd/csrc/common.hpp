@@ -58,6 +58,37 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Wave-wide sum and maximum by DPP: lanes combine within their 16-lane row
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror),
+// then the four row results are read by readlane and combined in row order.
+// Fixed order; every lane gets the result.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, make_int2(lo, hi));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(b.x, lane),
+                                              __builtin_amdgcn_readlane(b.y, lane)));
+}
+__device__ __forceinline__ double wave_sum_rows(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return ((lane_f64(v, 0) + lane_f64(v, 16)) + lane_f64(v, 32)) + lane_f64(v, 48);
+}
+__device__ __forceinline__ double wave_max_rows(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), lane_f64(v, 32)), lane_f64(v, 48));
+}
+
 // Workspace carving: bump allocator with 256-byte alignment.
 struct Carve {
   size_t off = 0;

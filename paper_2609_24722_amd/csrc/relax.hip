@@ -454,30 +454,49 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   }
 }
 
-// Sum the split partials (fixed order) into the trial gradient / energy terms.
-__global__ void k_exact_sum(RelaxDev R, int grad) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= R.ntot) return;
-  double g0 = 0.0, g1 = 0.0, e = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0;
-  for (int s = 0; s < R.splits; ++s) {
-    const size_t q = (size_t)s * R.ntot + a;
-    g0 += R.px[q];
-    g1 += R.py[q];
-    e += R.pe[q];
-    if (grad) {
-      k0 += R.pkxx[q];
-      k1 += R.pkxy[q];
-      k2 += R.pkyy[q];
+// Sum the split partials into the trial gradient / energy terms.  One
+// workgroup per 64 actives: wave w sums the splits w, w + kESW, ... in
+// increasing order, then the wave partials are added in wave order, so the
+// order is fixed and a long split list is read by kESW waves at once.
+constexpr int kESW = 8;
+
+__global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int grad) {
+  __shared__ double part[kESW - 1][6][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a = blockIdx.x * 64 + lane;
+  const bool ok = a < R.ntot;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    for (int sp = w; sp < R.splits; sp += kESW) {
+      const size_t q = (size_t)sp * R.ntot + a;
+      v[0] += R.px[q];
+      v[1] += R.py[q];
+      v[2] += R.pe[q];
+      if (grad) {
+        v[3] += R.pkxx[q];
+        v[4] += R.pkxy[q];
+        v[5] += R.pkyy[q];
+      }
     }
   }
-  if (grad) {
-    R.hgx[a] = g0;
-    R.hgy[a] = g1;
-    R.hkxx[a] = k0;
-    R.hkxy[a] = k1;
-    R.hkyy[a] = k2;
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) part[w - 1][c][lane] = v[c];
   }
-  R.eterm[a] = e;
+  __syncthreads();
+  if (w > 0 || !ok) return;
+  for (int q = 0; q < kESW - 1; ++q) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] += part[q][c][lane];
+  }
+  if (grad) {
+    R.hgx[a] = v[0];
+    R.hgy[a] = v[1];
+    R.hkxx[a] = v[3];
+    R.hkxy[a] = v[4];
+    R.hkyy[a] = v[5];
+  }
+  R.eterm[a] = v[2];
 }
 
 // ------------------------------------------------------------ model evaluation --
@@ -658,24 +677,84 @@ constexpr int kUpd = 1024;
 constexpr int kUpdWaves = kUpd / 64;
 constexpr int kRegJ = 4;  // actives per thread held in registers by the two-loop
 
-// Workgroup sum and maximum (fixed order: waves' results in wave order).
-__device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+// Workgroup reductions of a kUpd-thread workgroup: each wave reduces by DPP
+// (wave_sum_rows, wave_max_rows), the wave results go to LDS and every
+// thread adds them in wave order.  The LDS partials alternate between two
+// buffers, so one barrier per reduction suffices: a buffer is written again
+// two reductions later, after every thread has passed the barrier of the
+// reduction in between (and so has finished reading it).  Every thread of
+// the workgroup must take part in every reduction, in the same order.
+struct WgRed {
+  double* buf;  // LDS, 2 * 3 * kUpdWaves doubles
+  int par;
+  __device__ explicit WgRed(double* b) : buf(b), par(0) {}
+  __device__ double* next() {
+    double* r = buf + par * 3 * kUpdWaves;
+    par ^= 1;
+    return r;
+  }
+};
+#define WG_RED_LDS(name) __shared__ double name##_buf[2 * 3 * kUpdWaves]; WgRed name(name##_buf)
+
+__device__ double block_sum(double v, WgRed& R) {
+  v = wave_sum_rows(v);
+  double* r = R.next();
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
   __syncthreads();
   double t = 0.0;
-  for (int q = 0; q < kUpdWaves; ++q) t += red[q];
+  for (int q = 0; q < kUpdWaves; ++q) t += r[q];
   return t;
 }
-__device__ double block_max(double v, double* red) {
-  v = wave_max(v);
+__device__ double block_max(double v, WgRed& R) {
+  v = wave_max_rows(v);
+  double* r = R.next();
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = red[0];
-  for (int q = 1; q < kUpdWaves; ++q) t = fmax(t, red[q]);
+  double t = r[0];
+  for (int q = 1; q < kUpdWaves; ++q) t = fmax(t, r[q]);
   return t;
+}
+// three sums in one pass
+__device__ void block_sum3(double& a, double& b, double& c, WgRed& R) {
+  a = wave_sum_rows(a);
+  b = wave_sum_rows(b);
+  c = wave_sum_rows(c);
+  double* r = R.next();
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    r[3 * w] = a;
+    r[3 * w + 1] = b;
+    r[3 * w + 2] = c;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0, tc = 0.0;
+  for (int q = 0; q < kUpdWaves; ++q) {
+    ta += r[3 * q];
+    tb += r[3 * q + 1];
+    tc += r[3 * q + 2];
+  }
+  a = ta;
+  b = tb;
+  c = tc;
+}
+// a sum and a maximum in one pass
+__device__ void block_sum_max(double& sm, double& mx, WgRed& R) {
+  sm = wave_sum_rows(sm);
+  mx = wave_max_rows(mx);
+  double* r = R.next();
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    r[3 * w] = sm;
+    r[3 * w + 1] = mx;
+  }
+  __syncthreads();
+  double ts = 0.0, tm = r[1];
+  for (int q = 0; q < kUpdWaves; ++q) {
+    ts += r[3 * q];
+    tm = fmax(tm, r[3 * q + 1]);
+  }
+  sm = ts;
+  mx = tm;
 }
 
 // reduced gradient component magnitude at position (px, py) with gradient g:
@@ -782,7 +861,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   HT* const Sy = reinterpret_cast<HT*>(R.Sy);
   HT* const Yx = reinterpret_cast<HT*>(R.Yx);
   HT* const Yy = reinterpret_cast<HT*>(R.Yy);
-  __shared__ double red[kUpdWaves];
+  WG_RED_LDS(red);
   __shared__ double s_alf[kMaxMem];
   __shared__ int s_flag;
   const int p = blockIdx.x, t = threadIdx.x;
@@ -793,34 +872,34 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   const int m = R.m;
   double* rho = R.rho + (size_t)p * m;
 
-  // energy of the trial (fixed-order block sum of per-active terms)
-  double e = 0.0;
-  for (int a = a0 + t; a < a1; a += kUpd) e += R.eterm[a];
-  const double Et = block_sum(e, red);
+  // energy of the trial (fixed-order block sum of per-active terms) and the
+  // directional derivatives along the step in optimisation coordinates:
+  // pred = grad(z).s, dpt = grad(zt).s; a held charge's step is the angle
+  // alpha*d (its Cartesian displacement has a second-order radial part that
+  // the large wall reaction would weigh), a free charge's is zt - z
+  double e = 0.0, pr = 0.0, pt = 0.0;
+  for (int a = a0 + t; a < a1; a += kUpd) {
+    e += R.eterm[a];
+    if (s.init) continue;
+    if (R.held[a]) {
+      const double st = s.alpha * R.dx[a];
+      pr += (-R.gx[a] * R.zy[a] + R.gy[a] * R.zx[a]) * st;
+      pt += (-R.hgx[a] * R.ty[a] + R.hgy[a] * R.tx[a]) * st;
+    } else {
+      const double ddx = R.tx[a] - R.zx[a], ddy = R.ty[a] - R.zy[a];
+      pr += R.gx[a] * ddx + R.gy[a] * ddy;
+      pt += R.hgx[a] * ddx + R.hgy[a] * ddy;
+    }
+  }
+  block_sum3(e, pr, pt, red);
+  const double Et = e;
   bool accept;
   bool nonfinite = !isfinite(Et);
   double shrink = 0.5;  // backtracking factor when the trial is rejected
   if (s.init) {
     accept = true;
   } else {
-    // directional derivatives along the step in optimisation coordinates:
-    // pred = grad(z).s, dpt = grad(zt).s; a held charge's step is the angle
-    // alpha*d (its Cartesian displacement has a second-order radial part that
-    // the large wall reaction would weigh), a free charge's is zt - z
-    double pr = 0.0, pt = 0.0;
-    for (int a = a0 + t; a < a1; a += kUpd) {
-      if (R.held[a]) {
-        const double st = s.alpha * R.dx[a];
-        pr += (-R.gx[a] * R.zy[a] + R.gy[a] * R.zx[a]) * st;
-        pt += (-R.hgx[a] * R.ty[a] + R.hgy[a] * R.tx[a]) * st;
-      } else {
-        const double ddx = R.tx[a] - R.zx[a], ddy = R.ty[a] - R.zy[a];
-        pr += R.gx[a] * ddx + R.gy[a] * ddy;
-        pt += R.hgx[a] * ddx + R.hgy[a] * ddy;
-      }
-    }
-    const double pred = block_sum(pr, red);
-    const double dpt = block_sum(pt, red);
+    const double pred = pr, dpt = pt;
     const double dE = Et - s.E;
     const double noise = (s.use32 ? 1e-9 : R.noise_rel) * fabs(s.E);
     if (fabs(dE) > noise) {
@@ -872,7 +951,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         ssp += s0 * s0 + s1 * s1;
         yyp += y0 * y0 + y1 * y1;
       }
-      const double sy = block_sum(syp, red), ss = block_sum(ssp, red), yy = block_sum(yyp, red);
+      block_sum3(syp, ssp, yyp, red);
+      const double sy = syp, ss = ssp, yy = yyp;
       if (sy > 1e-12 * sqrt(ss * yy)) {
         if (t == 0) rho[k] = 1.0 / sy;
         s.head = (s.head + 1) % m;
@@ -959,12 +1039,14 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     s.head = 0;
   }
 
-  // new direction: two-loop recursion on the coordinate gradient.  For a
-  // patch of at most kRegJ * kUpd actives the vector stays in registers and
-  // each history pair is loaded once per loop, both halves issued before the
-  // reduction; larger patches keep it in memory.  Same arithmetic, same order.
+  // new direction: two-loop recursion on the coordinate gradient.  A
+  // thread's first kRegJ actives (a0 + t + j kUpd) keep the vector in
+  // registers; any further ones (patches above kRegJ * kUpd actives) keep it
+  // in R.dx, R.dy, touched only by their own thread, inside the same steps.
+  // Each thread sums its actives in increasing order, then the workgroup sum.
   __syncthreads();
-  if (a1 - a0 <= kRegJ * kUpd) {
+  {
+    const int tail0 = a0 + t + kRegJ * kUpd;
     double qx[kRegJ], qy[kRegJ];
 #pragma unroll
     for (int j = 0; j < kRegJ; ++j) {
@@ -972,28 +1054,59 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       qx[j] = qy[j] = 0.0;
       if (a < a1) coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], qx[j], qy[j]);
     }
-    for (int k = 0; k < s.mem; ++k) {
-      const int kk = (s.head - 1 - k + m) % m;
-      const size_t base = (size_t)kk * R.ntot;
-      HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
+    for (int a = tail0; a < a1; a += kUpd) {
+      double c0, c1;
+      coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      R.dx[a] = c0;
+      R.dy[a] = c1;
+    }
+    // FP32 history: pair k + 1 is loaded while pair k is reduced (FP64
+    // history has no registers to spare for it)
+    constexpr bool kPre = sizeof(HT) == 4;
+    HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
+    auto load_pair = [&](int k, HT* u0, HT* u1, HT* w0, HT* w1) {
+      const bool kin = k >= 0 && k < s.mem;  // pairs outside the memory read as zero
+      const size_t base = (size_t)((s.head - 1 - (kin ? k : 0) + m) % m) * R.ntot;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
         const int a = a0 + t + j * kUpd;
-        const bool ok = a < a1;
-        ux[j] = ok ? Sx[base + a] : (HT)0;
-        uy[j] = ok ? Sy[base + a] : (HT)0;
-        wx[j] = ok ? Yx[base + a] : (HT)0;
-        wy[j] = ok ? Yy[base + a] : (HT)0;
+        const bool ok = kin && a < a1;
+        u0[j] = ok ? Sx[base + a] : (HT)0;
+        u1[j] = ok ? Sy[base + a] : (HT)0;
+        w0[j] = ok ? Yx[base + a] : (HT)0;
+        w1[j] = ok ? Yy[base + a] : (HT)0;
       }
+    };
+    if (kPre) load_pair(0, ux, uy, wx, wy);
+    for (int k = 0; k < s.mem; ++k) {
+      const int kk = (s.head - 1 - k + m) % m;
+      const size_t base = (size_t)kk * R.ntot;
+      HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+      if (kPre)
+        load_pair(k + 1, nux, nuy, nwx, nwy);
+      else
+        load_pair(k, ux, uy, wx, wy);
       double v = 0.0;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
+      for (int a = tail0; a < a1; a += kUpd)
+        v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
       const double al = rho[kk] * block_sum(v, red);
       if (t == 0) s_alf[kk] = al;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
         qx[j] -= al * (double)wx[j];
         qy[j] -= al * (double)wy[j];
+        if (kPre) {
+          ux[j] = nux[j];
+          uy[j] = nuy[j];
+          wx[j] = nwx[j];
+          wy[j] = nwy[j];
+        }
+      }
+      for (int a = tail0; a < a1; a += kUpd) {
+        R.dx[a] -= al * (double)Yx[base + a];
+        R.dy[a] -= al * (double)Yy[base + a];
       }
     }
     // the preconditioner goes through memory (a loop, not unrolled: its
@@ -1021,28 +1134,36 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         qy[j] = R.dy[a];
       }
     }
+    if (kPre) load_pair(s.mem - 1, ux, uy, wx, wy);
     for (int k = s.mem - 1; k >= 0; --k) {
       const int kk = (s.head - 1 - k + m) % m;
       const size_t base = (size_t)kk * R.ntot;
-      HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
-#pragma unroll
-      for (int j = 0; j < kRegJ; ++j) {
-        const int a = a0 + t + j * kUpd;
-        const bool ok = a < a1;
-        wx[j] = ok ? Yx[base + a] : (HT)0;
-        wy[j] = ok ? Yy[base + a] : (HT)0;
-        ux[j] = ok ? Sx[base + a] : (HT)0;
-        uy[j] = ok ? Sy[base + a] : (HT)0;
-      }
+      HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+      if (kPre)
+        load_pair(k - 1, nux, nuy, nwx, nwy);
+      else
+        load_pair(k, ux, uy, wx, wy);
       double v = 0.0;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
+      for (int a = tail0; a < a1; a += kUpd)
+        v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
       const double be = rho[kk] * block_sum(v, red);
       const double coef = s_alf[kk] - be;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
         qx[j] += coef * (double)ux[j];
         qy[j] += coef * (double)uy[j];
+        if (kPre) {
+          ux[j] = nux[j];
+          uy[j] = nuy[j];
+          wx[j] = nwx[j];
+          wy[j] = nwy[j];
+        }
+      }
+      for (int a = tail0; a < a1; a += kUpd) {
+        R.dx[a] += coef * (double)Sx[base + a];
+        R.dy[a] += coef * (double)Sy[base + a];
       }
     }
 #pragma unroll
@@ -1053,69 +1174,26 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         R.dy[a] = qy[j];
       }
     }
-  } else {
-    for (int a = a0 + t; a < a1; a += kUpd) {
-      double c0, c1;
-      coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
-      R.dx[a] = c0;
-      R.dy[a] = c1;
-    }
-    __syncthreads();
-    for (int k = 0; k < s.mem; ++k) {
-      const int kk = (s.head - 1 - k + m) % m;
-      double v = 0.0;
-      for (int a = a0 + t; a < a1; a += kUpd) {
-        const size_t q = (size_t)kk * R.ntot + a;
-        v += (double)Sx[q] * R.dx[a] + (double)Sy[q] * R.dy[a];
-      }
-      const double al = rho[kk] * block_sum(v, red);
-      if (t == 0) s_alf[kk] = al;
-      for (int a = a0 + t; a < a1; a += kUpd) {
-        const size_t q = (size_t)kk * R.ntot + a;
-        R.dx[a] -= al * (double)Yx[q];
-        R.dy[a] -= al * (double)Yy[q];
-      }
-      __syncthreads();
-    }
-    for (int a = a0 + t; a < a1; a += kUpd) {
-      double r0, r1;
-      apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
-                 R.dx[a], R.dy[a], r0, r1);
-      R.dx[a] = r0;
-      R.dy[a] = r1;
-    }
-    __syncthreads();
-    for (int k = s.mem - 1; k >= 0; --k) {
-      const int kk = (s.head - 1 - k + m) % m;
-      double v = 0.0;
-      for (int a = a0 + t; a < a1; a += kUpd) {
-        const size_t q = (size_t)kk * R.ntot + a;
-        v += (double)Yx[q] * R.dx[a] + (double)Yy[q] * R.dy[a];
-      }
-      const double be = rho[kk] * block_sum(v, red);
-      const double coef = s_alf[kk] - be;
-      for (int a = a0 + t; a < a1; a += kUpd) {
-        const size_t q = (size_t)kk * R.ntot + a;
-        R.dx[a] += coef * (double)Sx[q];
-        R.dy[a] += coef * (double)Sy[q];
-      }
-      __syncthreads();
-    }
   }
   // d = -H g; fall back to scaled steepest descent if not a descent direction
+  // (the step length bound dm is taken in the same pass; the rare steepest
+  // descent fallback takes it again)
   double dg = 0.0, dm = 0.0;
   for (int a = a0 + t; a < a1; a += kUpd) {
     double c0, c1;
     const bool h = R.held[a];
     coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
-    R.dx[a] = -R.dx[a];
-    R.dy[a] = -R.dy[a];
-    dg += R.dx[a] * c0 + R.dy[a] * c1;
+    const double d0 = -R.dx[a], d1 = -R.dy[a];
+    R.dx[a] = d0;
+    R.dy[a] = d1;
+    dg += d0 * c0 + d1 * c1;
+    dm = fmax(dm, h ? fabs(d0) : sqrt(d0 * d0 + d1 * d1));
   }
-  dg = block_sum(dg, red);
+  block_sum_max(dg, dm, red);
   const bool steep = !(dg < 0.0);
-  for (int a = a0 + t; a < a1; a += kUpd) {
-    if (steep) {
+  if (steep) {
+    dm = 0.0;
+    for (int a = a0 + t; a < a1; a += kUpd) {
       double c0, c1, r0, r1;
       const bool h = R.held[a];
       coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
@@ -1123,11 +1201,10 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
                  r1);
       R.dx[a] = -r0;
       R.dy[a] = -r1;
+      dm = fmax(dm, h ? fabs(r0) : sqrt(r0 * r0 + r1 * r1));
     }
-    const double l = R.held[a] ? fabs(R.dx[a]) : sqrt(R.dx[a] * R.dx[a] + R.dy[a] * R.dy[a]);
-    dm = fmax(dm, l);
+    dm = block_max(dm, red);
   }
-  dm = block_max(dm, red);
   const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
   s.alpha = 1.0;
   for (int a = a0 + t; a < a1; a += kUpd) {
@@ -1184,7 +1261,7 @@ __global__ void k_count_running(RelaxDev R) {
 // of their current exact gradient.
 __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double frac,
                                                 double tol32, double* __restrict__ ptol) {
-  __shared__ double red[kUpdWaves];
+  WG_RED_LDS(red);
   const int p = blockIdx.x, t = threadIdx.x;
   PState s = R.st[p];
   if (s.status == kNonFinite || s.status == kDone) return;
@@ -1212,7 +1289,7 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
                                                  double* __restrict__ gtan,
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ status) {
-  __shared__ double red[kUpdWaves];
+  WG_RED_LDS(red);
   const int p = blockIdx.x, t = threadIdx.x;
   const PState s = R.st[p];
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
@@ -1241,7 +1318,7 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
 }
 
 __global__ __launch_bounds__(kUpd) void k_finish_delta(RelaxDev R, double* __restrict__ dE) {
-  __shared__ double red[kUpdWaves];
+  WG_RED_LDS(red);
   const int p = blockIdx.x, t = threadIdx.x;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   double e = 0.0;
@@ -1505,6 +1582,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   if ((rc = hip_status(hipMemsetAsync(D.maskAH, 0, sizeof(uint64_t) * n_patches * R.nbN, st))))
     return rc;
   const int tb = (int)((ntot + 255) / 256);
+  const int tb64 = (int)((ntot + 63) / 64);
   if ((rc = hip_status(hipMemsetAsync(D.err, 0, sizeof(int32_t), st)))) return rc;
   hipLaunchKernelGGL(k_setup_actives, dim3(tb), dim3(256), 0, st, D, x_start, y_start);
   {
@@ -1520,10 +1598,12 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     RelaxDev E = D;
     E.eval_all = all;
     hipLaunchKernelGGL(k_exact<kGrad>, eg, eb, 0, st, E);
-    hipLaunchKernelGGL(k_exact_sum, dim3(tb), dim3(256), 0, st, E, 1);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, E, 1);
   };
 
-  if (o.precision == CD_FP64) {
+  if (o.max_iter == 0) {
+    // evaluation only: the outputs describe the (projected) start positions
+  } else if (o.precision == CD_FP64) {
     D.tol = o.gtol;
     if ((rc = run_rounds(R, st, max_rounds, false, [&]() { exact_grad(0); }))) return rc;
   } else {
@@ -1611,7 +1691,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                      o.precision == CD_FP64 ? 1 : 0, x_out, y_out, e_sub, gtan_inf, iters, status);
   if (dE) {
     hipLaunchKernelGGL(k_exact<kDelta>, eg, eb, 0, st, D);
-    hipLaunchKernelGGL(k_exact_sum, dim3(tb), dim3(256), 0, st, D, 0);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, D, 0);
     hipLaunchKernelGGL(k_finish_delta, dim3(n_patches), dim3(kUpd), 0, st, D, dE);
   }
   rc = hip_status(hipGetLastError());
