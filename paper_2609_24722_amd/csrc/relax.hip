@@ -434,33 +434,30 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   }
   if (!ok) return;
   const size_t q = (size_t)blockIdx.y * R.ntot + a;
-  if (MODE == kFar) {
-    R.zrx[a] = xi;  // kFar runs with a single split
+  R.px[q] = G0;
+  R.py[q] = G1;
+  if (MODE != kFar) R.pe[q] = Ee + Ec;
+  if (MODE != kDelta) {
+    R.pkxx[q] = G2;
+    R.pkxy[q] = G3;
+    R.pkyy[q] = G4;
+  }
+  if (MODE == kFar && blockIdx.y == 0) {
+    R.zrx[a] = xi;  // the expansion point
     R.zry[a] = yi;
-    R.fgx[a] = G0;
-    R.fgy[a] = G1;
-    R.fhxx[a] = G2;
-    R.fhxy[a] = G3;
-    R.fhyy[a] = G4;
-  } else {
-    R.px[q] = G0;
-    R.py[q] = G1;
-    R.pe[q] = Ee + Ec;
-    if (MODE == kGrad) {
-      R.pkxx[q] = G2;
-      R.pkxy[q] = G3;
-      R.pkyy[q] = G4;
-    }
   }
 }
 
-// Sum the split partials into the trial gradient / energy terms.  One
-// workgroup per 64 actives: wave w sums the splits w, w + kESW, ... in
-// increasing order, then the wave partials are added in wave order, so the
-// order is fixed and a long split list is read by kESW waves at once.
+// Sum the split partials: mode kDelta the energy terms, kGrad also the
+// trial gradient and Hessian blocks, kFar the far-field gradient and Hessian
+// (no energy).  One workgroup per 64 actives: wave w sums the splits w,
+// w + kESW, ... in increasing order, then the wave partials are added in
+// wave order, so the order is fixed and a long split list is read by kESW
+// waves at once.
 constexpr int kESW = 8;
 
-__global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int grad) {
+__global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
+  const bool grad = mode != kDelta;
   __shared__ double part[kESW - 1][6][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a = blockIdx.x * 64 + lane;
@@ -471,7 +468,7 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int grad) {
       const size_t q = (size_t)sp * R.ntot + a;
       v[0] += R.px[q];
       v[1] += R.py[q];
-      v[2] += R.pe[q];
+      if (mode != kFar) v[2] += R.pe[q];
       if (grad) {
         v[3] += R.pkxx[q];
         v[4] += R.pkxy[q];
@@ -488,6 +485,14 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int grad) {
   for (int q = 0; q < kESW - 1; ++q) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c] += part[q][c][lane];
+  }
+  if (mode == kFar) {
+    R.fgx[a] = v[0];
+    R.fgy[a] = v[1];
+    R.fhxx[a] = v[3];
+    R.fhxy[a] = v[4];
+    R.fhyy[a] = v[5];
+    return;
   }
   if (grad) {
     R.hgx[a] = v[0];
@@ -1598,7 +1603,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     RelaxDev E = D;
     E.eval_all = all;
     hipLaunchKernelGGL(k_exact<kGrad>, eg, eb, 0, st, E);
-    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, E, 1);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, E, (int)kGrad);
   };
 
   if (o.max_iter == 0) {
@@ -1622,8 +1627,6 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       return rc;
     hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 1, R.hcount);
     RelaxDev Df = D;
-    Df.splits = 1;
-    Df.jb = R.nbN;
     Df.eval_all = 1;
     const int hb = (hp[n_patches] + 255) / 256;
     hipLaunchKernelGGL(k_model_prep, dim3(tb > hb ? tb : hb), dim3(256), 0, st, D, 1);
@@ -1648,7 +1651,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     const bool trace = g_trace;
     for (int outer = 0; outer < outer_max; ++outer) {
       hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
-      hipLaunchKernelGGL(k_exact<kFar>, dim3((D.nblk + 3) / 4, 1), eb, 0, st, Df);
+      hipLaunchKernelGGL(k_exact<kFar>, eg, eb, 0, st, Df);
+      hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, Df, (int)kFar);
       model(1);
       hipLaunchKernelGGL(k_check, dim3(n_patches), dim3(kUpd), 0, st, D, o.gtol, 0.01, tol32,
                          ptol_ws);
@@ -1691,7 +1695,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                      o.precision == CD_FP64 ? 1 : 0, x_out, y_out, e_sub, gtan_inf, iters, status);
   if (dE) {
     hipLaunchKernelGGL(k_exact<kDelta>, eg, eb, 0, st, D);
-    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, D, 0);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, D, (int)kDelta);
     hipLaunchKernelGGL(k_finish_delta, dim3(n_patches), dim3(kUpd), 0, st, D, dE);
   }
   rc = hip_status(hipGetLastError());
