@@ -86,6 +86,11 @@ def lib():
         L.orc_esub_hvp.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _D, _D, _D, _D, _D, _D]
         L.orc_reduce_grad.restype = ctypes.c_double
         L.orc_reduce_grad.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D, _D, _I32]
+        L.orc_reduce_grad_bi.restype = ctypes.c_double
+        L.orc_reduce_grad_bi.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _I32, ctypes.c_double, _D, _D, _I32]
+        L.orc_relax_bi.restype = None
+        L.orc_relax_bi.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _I32, ctypes.c_double, _D, _D,
+                                   ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
         L.orc_relax.restype = None
         L.orc_relax.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _D, _D,
                                 ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
@@ -221,8 +226,11 @@ def esub_hvp(x, y, idx, xa, ya, vx, vy):
     return hx, hy
 
 
-def reduce_grad(xa, ya, gx, gy):
-    """Hard-wall KKT reduction (Eq. 3): returns (tx, ty, held, inf_norm)."""
+def reduce_grad(xa, ya, gx, gy, pin=None, sigma: float = 1.0):
+    """KKT reduction of the gradient: returns (tx, ty, held, inf_norm).
+    Hard wall of Eq. 3 by default; with pin (flags per charge) and sigma the
+    border-interior constraint of Sec. II.B (pinned charges on the unit
+    circle, the others inside radius sigma)."""
     xa, pxa = _d(xa)
     ya, pya = _d(ya)
     gx, pgx = _d(gx)
@@ -230,8 +238,13 @@ def reduce_grad(xa, ya, gx, gy):
     tx = np.empty(xa.size)
     ty = np.empty(xa.size)
     cons = np.empty(xa.size, dtype=np.int32)
-    m = lib().orc_reduce_grad(xa.size, pxa, pya, pgx, pgy, tx.ctypes.data_as(_D),
-                              ty.ctypes.data_as(_D), cons.ctypes.data_as(_I32))
+    if pin is None:
+        m = lib().orc_reduce_grad(xa.size, pxa, pya, pgx, pgy, tx.ctypes.data_as(_D),
+                                  ty.ctypes.data_as(_D), cons.ctypes.data_as(_I32))
+    else:
+        pin, ppin = _i(pin)
+        m = lib().orc_reduce_grad_bi(xa.size, pxa, pya, pgx, pgy, ppin, float(sigma), tx.ctypes.data_as(_D),
+                                     ty.ctypes.data_as(_D), cons.ctypes.data_as(_I32))
     return tx, ty, cons, m
 
 
@@ -257,8 +270,10 @@ def spacing(n: int) -> float:
 
 
 def relax(x, y, idx, xa=None, ya=None, gtol=1e-10, max_iter=5000, lbfgs_m=8,
-          newton_tol=None, step0=None, cg_max=200):
+          newton_tol=None, step0=None, cg_max=200, pin=None, sigma: float = 1.0):
     """Local relaxation of the active set (Sec. II.C step 4, Cartesian reading).
+    pin (flags per active) and sigma select the border-interior constraint of
+    Sec. II.B instead of the hard wall.
 
     Returns (xa, ya, stats dict)."""
     x, px = _d(x)
@@ -274,8 +289,13 @@ def relax(x, y, idx, xa=None, ya=None, gtol=1e-10, max_iter=5000, lbfgs_m=8,
                   float(newton_tol if newton_tol is not None else 1e-3 / h ** 2),
                   float(step0 if step0 is not None else 0.05 * h), int(cg_max))
     st = RelaxStats()
-    lib().orc_relax(x.size, px, py, idx.size, pidx, xa.ctypes.data_as(_D), ya.ctypes.data_as(_D),
-                    ctypes.byref(o), ctypes.byref(st))
+    if pin is None:
+        lib().orc_relax(x.size, px, py, idx.size, pidx, xa.ctypes.data_as(_D), ya.ctypes.data_as(_D),
+                        ctypes.byref(o), ctypes.byref(st))
+    else:
+        pin, ppin = _i(pin)
+        lib().orc_relax_bi(x.size, px, py, idx.size, pidx, ppin, float(sigma), xa.ctypes.data_as(_D),
+                           ya.ctypes.data_as(_D), ctypes.byref(o), ctypes.byref(st))
     return xa, ya, {"iters": st.iters, "newton_steps": st.newton_steps,
                     "status": st.status, "gtan_inf": st.gtan_inf}
 

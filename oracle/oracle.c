@@ -33,6 +33,9 @@
  *   orc_relax        local relaxation of one subdomain (Sec. II.C step 4):
  *                    L-BFGS on free and wall-held coordinates, then
  *                    truncated Newton on the tangent-space Hessian.
+ *   orc_reduce_grad_bi, orc_relax_bi  the same under the border-interior
+ *                    constraint of Sec. II.B: boundary charges pinned to the
+ *                    unit circle, the others confined to |r| <= sigma.
  */
 #include <math.h>
 #include <stdint.h>
@@ -366,17 +369,23 @@ void orc_esub_hvp(int64_t n, const double *x, const double *y, int64_t na,
  * held charge the reduced gradient is the tangential part of g; otherwise it
  * is g.  cons[i] = 1 for held charges.  Returns max_i |reduced g| (inf-norm
  * over the 2na components). */
-double orc_reduce_grad(int64_t na, const double *xa, const double *ya, const double *gx,
-                       const double *gy, double *tx, double *ty, int32_t *cons) {
+/* Border-interior variant (Sec. II.B): pin[a] != 0 marks a boundary charge,
+ * pinned to the unit circle (always held, reduced gradient = its tangential
+ * part); every other charge has its wall at radius sigma (on the wall when
+ * |r| >= sigma (1 - 1e-14)).  pin = NULL and sigma = 1 give the hard wall. */
+double orc_reduce_grad_bi(int64_t na, const double *xa, const double *ya, const double *gx,
+                          const double *gy, const int32_t *pin, double sigma, double *tx,
+                          double *ty, int32_t *cons) {
   double m = 0.0;
   for (int64_t a = 0; a < na; ++a) {
     double r = sqrt(xa[a] * xa[a] + ya[a] * ya[a]);
     double ox = gx[a], oy = gy[a];
     int c = 0;
-    if (r >= 1.0 - 1e-14) {
+    const int pinned = pin && pin[a];
+    if (pinned || r >= sigma * (1.0 - 1e-14)) {
       double ux = xa[a] / r, uy = ya[a] / r;
       double gr = gx[a] * ux + gy[a] * uy;
-      if (gr < 0.0) {
+      if (pinned || gr < 0.0) {
         ox = gx[a] - gr * ux;
         oy = gy[a] - gr * uy;
         c = 1;
@@ -391,12 +400,30 @@ double orc_reduce_grad(int64_t na, const double *xa, const double *ya, const dou
   return m;
 }
 
-static void project(int64_t na, double *xa, double *ya) {
+double orc_reduce_grad(int64_t na, const double *xa, const double *ya, const double *gx,
+                       const double *gy, double *tx, double *ty, int32_t *cons) {
+  return orc_reduce_grad_bi(na, xa, ya, gx, gy, NULL, 1.0, tx, ty, cons);
+}
+
+/* The constraint of one relax: pinned boundary charges and the interior wall. */
+typedef struct {
+  const int32_t *pin;
+  double sigma;
+} wall_t;
+
+/* Feasible projection: a pinned charge onto the unit circle, any other
+ * charge beyond sigma onto the circle of radius sigma. */
+static void project(int64_t na, double *xa, double *ya, const wall_t *w) {
   for (int64_t a = 0; a < na; ++a) {
     double r = sqrt(xa[a] * xa[a] + ya[a] * ya[a]);
-    if (r > 1.0) {
-      xa[a] /= r;
-      ya[a] /= r;
+    if (w->pin && w->pin[a]) {
+      if (r > 0.0) {
+        xa[a] /= r;
+        ya[a] /= r;
+      }
+    } else if (r > w->sigma) {
+      xa[a] *= w->sigma / r;
+      ya[a] *= w->sigma / r;
     }
   }
 }
@@ -437,7 +464,7 @@ static void to_coords(int64_t na, const double *xa, const double *ya, const doub
 /* Position after the coordinate step scale*s: free charges translate (then
  * are projected onto |r| <= 1), held charges rotate by the angle step. */
 static void take_step(int64_t na, const double *xa, const double *ya, const int32_t *held,
-                      const double *s, double scale, double *nx, double *ny) {
+                      const double *s, double scale, double *nx, double *ny, const wall_t *w) {
   for (int64_t a = 0; a < na; ++a) {
     if (held[a]) {
       double th = scale * s[2 * a];
@@ -449,17 +476,19 @@ static void take_step(int64_t na, const double *xa, const double *ya, const int3
       ny[a] = ya[a] + scale * s[2 * a + 1];
     }
   }
-  project(na, nx, ny);
+  project(na, nx, ny, w);
 }
 
-/* Held-set rule of Eq. 3's hard wall: held iff on the wall and g . r_hat < 0. */
+/* Held-set rule of Eq. 3's hard wall: held iff on the wall and g . r_hat < 0;
+ * a pinned boundary charge is always held. */
 static int update_held(int64_t na, const double *xa, const double *ya, const double *gx,
-                       const double *gy, int32_t *held, int32_t *changed) {
+                       const double *gy, int32_t *held, int32_t *changed, const wall_t *w) {
   int any = 0;
   for (int64_t a = 0; a < na; ++a) {
     double r = sqrt(xa[a] * xa[a] + ya[a] * ya[a]);
     int h = 0;
-    if (r >= 1.0 - 1e-14) h = (gx[a] * xa[a] + gy[a] * ya[a]) < 0.0;
+    if (w->pin && w->pin[a]) h = 1;
+    else if (r >= w->sigma * (1.0 - 1e-14)) h = (gx[a] * xa[a] + gy[a] * ya[a]) < 0.0;
     changed[a] = (h != held[a]);
     any |= changed[a];
     held[a] = h;
@@ -509,9 +538,10 @@ static double dot(int64_t m, const double *a, const double *b) {
  * reduced gradient is below newton_tol, truncated-Newton steps solve the
  * tangent-Hessian system by CG and are accepted when the reduced gradient
  * shrinks.  Convergence: inf-norm of the reduced gradient <= gtol. */
-void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
-               const int32_t *idx, double *xa, double *ya, const orc_relax_opts *o,
-               orc_relax_stats *st) {
+void orc_relax_bi(int64_t n, const double *x, const double *y, int64_t na,
+                  const int32_t *idx, const int32_t *pin, double sigma, double *xa, double *ya,
+                  const orc_relax_opts *o, orc_relax_stats *st) {
+  const wall_t wall = {pin, sigma}, *w = &wall;
   const int64_t m2 = 2 * na;
   const int M = o->lbfgs_m > 0 ? o->lbfgs_m : 8;
   double *gc = malloc(sizeof(double) * m2), *gcn = malloc(sizeof(double) * m2);
@@ -532,10 +562,10 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
   st->newton_steps = 0;
   st->status = 1;
 
-  project(na, xa, ya);
+  project(na, xa, ya, w);
   orc_esub(n, x, y, na, idx, xa, ya, gx, gy);
-  update_held(na, xa, ya, gx, gy, held, chg);
-  double gi = orc_reduce_grad(na, xa, ya, gx, gy, NULL, NULL, NULL);
+  update_held(na, xa, ya, gx, gy, held, chg, w);
+  double gi = orc_reduce_grad_bi(na, xa, ya, gx, gy, pin, sigma, NULL, NULL, NULL);
   to_coords(na, xa, ya, gx, gy, held, gc);
 
   for (int it = 0; it < o->max_iter; ++it) {
@@ -571,15 +601,15 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
       }
       double scale = 1.0;
       for (int h = 0; h < 8 && !took; ++h, scale *= 0.5) {
-        take_step(na, xa, ya, held, cx, scale, nx, ny);
+        take_step(na, xa, ya, held, cx, scale, nx, ny, w);
         orc_esub(n, x, y, na, idx, nx, ny, ngx, ngy);
-        double gin = orc_reduce_grad(na, nx, ny, ngx, ngy, NULL, NULL, NULL);
+        double gin = orc_reduce_grad_bi(na, nx, ny, ngx, ngy, pin, sigma, NULL, NULL, NULL);
         if (gin < gi) {
           memcpy(xa, nx, sizeof(double) * na);
           memcpy(ya, ny, sizeof(double) * na);
           memcpy(gx, ngx, sizeof(double) * na);
           memcpy(gy, ngy, sizeof(double) * na);
-          update_held(na, xa, ya, gx, gy, held, chg);
+          update_held(na, xa, ya, gx, gy, held, chg, w);
           to_coords(na, xa, ya, gx, gy, held, gc);
           gi = gin;
           took = 1;
@@ -631,7 +661,7 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
       }
       double al = 1.0;
       for (int ls = 0; ls < 40; ++ls, al *= 0.5) {
-        take_step(na, xa, ya, held, d, al, nx, ny);
+        take_step(na, xa, ya, held, d, al, nx, ny, w);
         double pred = 0.0;
         for (int64_t a = 0; a < na; ++a) {
           if (held[a]) pred += gc[2 * a] * al * d[2 * a];
@@ -677,7 +707,7 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
         head = (head + 1) % M;
         if (nmem < M) nmem++;
       }
-      if (update_held(na, xa, ya, gx, gy, held, chg)) {
+      if (update_held(na, xa, ya, gx, gy, held, chg, w)) {
         /* a charge changed coordinates: drop its components from the history */
         for (int k = 0; k < nmem; ++k) {
           int s = (head - 1 - k + M) % M;
@@ -689,7 +719,7 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
         }
       }
       to_coords(na, xa, ya, gx, gy, held, gc);
-      gi = orc_reduce_grad(na, xa, ya, gx, gy, NULL, NULL, NULL);
+      gi = orc_reduce_grad_bi(na, xa, ya, gx, gy, pin, sigma, NULL, NULL, NULL);
     }
     if (!took) {
       st->status = 2;
@@ -702,4 +732,10 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
   free(gx); free(gy); free(nx); free(ny); free(ngx); free(ngy); free(wx); free(wy);
   free(hx); free(hy); free(cr); free(cp); free(cHp); free(cx); free(X0); free(Y0);
   free(held); free(chg);
+}
+
+void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
+               const int32_t *idx, double *xa, double *ya, const orc_relax_opts *o,
+               orc_relax_stats *st) {
+  orc_relax_bi(n, x, y, na, idx, NULL, 1.0, xa, ya, o, st);
 }
