@@ -148,12 +148,21 @@ typedef struct {
                         (0 = 3e-2 / h^2) */
   double halo_width; /* CD_MIXED: halo width in units of h (0 = 4) */
   double step0;      /* largest displacement of an L-BFGS trial step (0 = 0.1 h) */
+  /* Border-interior split (Sec. II.B); both zero/NULL give the hard wall of
+   * Eq. 3 for every charge. */
+  double sigma;              /* wall radius of the charges not pinned, in (0, 1]
+                                (0 = 1) */
+  const int32_t* boundary;   /* device int32 [n] or NULL: nonzero marks a boundary
+                                charge, pinned to the unit circle (it moves only
+                                along it); starts are projected accordingly */
 } cd_relax_opts;
 
 /* Relax every patch of the batch (Sec. II.C step 4) against the frozen
  * snapshot (x, y)[n]: minimise E_sub = sum_{i in A} e_i (Eqs. 6-7, 1/2 on
  * active-active pairs) over the active positions subject to |r| <= 1 (Eq. 3),
- * by L-BFGS with wall-held charges moving on the circle.
+ * or under the border-interior split of opts (boundary charges on the unit
+ * circle, the others within sigma), by L-BFGS with wall-held charges moving
+ * on their circle.
  *   x_start, y_start: packed start positions [patch_ptr[P]] (device) or both
  *     NULL for the snapshot positions; starts outside the disk are projected.
  *   x_out, y_out (nullable pair): packed relaxed positions.
@@ -243,6 +252,20 @@ int zone_patches(const double* x, const double* y, int64_t n, int32_t n_zones, c
 int zone_batches(const double* cx, const double* cy, const double* rz, int32_t n_zones,
                  double gap, int32_t cap, int32_t keep_order, int32_t* batch,
                  int32_t* n_batches);
+
+/* Border-interior split (Sec. II.B).  border_count: N_b of Eq. 4,
+ * 2.84328 N^(2/3) - 0.530196 N^(1/3) - 2.32866 rounded to the nearest integer
+ * and clamped to [0, n] (6099 at N = 1e5).  border_sigma0: the initial
+ * interior radius of Eq. 5, 1 - 1/(2 sqrt(N)).  Host code. */
+int32_t border_count(int64_t n);
+double border_sigma0(int64_t n);
+
+/* Boundary charges: flags[n] (device int32) = 1 for the nb charges farthest
+ * from the centre by (x*x) + (y*y) (each operation rounded once in FP64),
+ * ties to the lower index, 0 for the others.  0 <= nb <= n.  One workgroup;
+ * needs no workspace; does not synchronise. */
+int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_t* flags,
+                 void* stream);
 
 /* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
  * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE

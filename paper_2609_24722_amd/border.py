@@ -1,0 +1,54 @@
+"""ctypes binding of the border-interior entry points (border_count,
+border_sigma0, border_split): argument marshalling only.
+
+Sec. II.B splits the charges into N_b boundary charges pinned to the unit
+circle and interior charges confined to |r| <= sigma, sigma rising from the
+value of Eq. 5 to 1; relax_subdomains takes the flags and sigma.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import ops
+
+
+def _lib():
+    L = ops.lib()
+    if not getattr(L, "_border_bound", False):
+        L.border_count.restype = ctypes.c_int32
+        L.border_count.argtypes = [ctypes.c_int64]
+        L.border_sigma0.restype = ctypes.c_double
+        L.border_sigma0.argtypes = [ctypes.c_int64]
+        L.border_split.restype = ctypes.c_int
+        L.border_split.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+        L._border_bound = True
+    return L
+
+
+def boundary_count(n: int) -> int:
+    """N_b of Eq. 4 (nearest integer)."""
+    return int(_lib().border_count(int(n)))
+
+
+def sigma0(n: int) -> float:
+    """Initial interior radius of Eq. 5."""
+    return float(_lib().border_sigma0(int(n)))
+
+
+def sigma_ramp(k: int, stages: int, n: int) -> float:
+    """Interior radius of stage k = 0..stages, linear from sigma0 to 1."""
+    s0 = sigma0(n)
+    return s0 + (1.0 - s0) * (k / stages) if stages > 0 else 1.0
+
+
+def border_split(x, y, nb: int):
+    """Device int32 flags: 1 for the nb charges farthest from the centre."""
+    dev = ops._chk(x, y)
+    n = x.numel()
+    flags = torch.empty(n, dtype=torch.int32, device=dev)
+    ops.check(_lib().border_split(x.data_ptr(), y.data_ptr(), n, int(nb), flags.data_ptr(),
+                                  ops.stream_ptr(dev)), "border_split")
+    return flags

@@ -1,0 +1,118 @@
+// Border-interior split of the charges (paper Sec. II.B): the boundary
+// population of Eq. 4, the initial interior radius of Eq. 5, and which
+// charges are boundary charges (the N_b farthest from the centre).
+//
+// k_border_select: one 1024-thread workgroup.  The key of charge i is the
+// bit pattern of r2 = (x*x) + (y*y) (separately rounded, non-negative, so it
+// orders like the value), complemented so that far charges come first; an
+// exact 8-pass radix select finds the N_b-th smallest key, then every charge
+// below it and, among charges equal to it, the lowest indices are flagged.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace cd {
+
+constexpr int kBT = 1024;
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ uint64_t border_key(double x, double y) {
+  const double a = x * x, b = y * y;
+  const double r2 = a + b;
+  return ~(uint64_t)__double_as_longlong(r2);
+}
+#pragma clang fp contract(on)
+
+__global__ __launch_bounds__(kBT) void k_border_select(const double* __restrict__ x,
+                                                       const double* __restrict__ y, int n,
+                                                       int nb, int32_t* __restrict__ flags) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix, s_mask;
+  __shared__ uint32_t s_need;
+  __shared__ uint32_t lt_cnt[kBT], eq_cnt[kBT];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    s_prefix = 0;
+    s_mask = 0;
+    s_need = (uint32_t)nb;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    if (t < 256) hist[t] = 0;
+    __syncthreads();
+    const uint64_t pre = s_prefix, msk = s_mask;
+    for (int j = t; j < n; j += kBT) {
+      const uint64_t key = border_key(x[j], y[j]);
+      if ((key & msk) == pre) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+      uint32_t need = s_need, b = 0;
+      while (b < 255 && hist[b] < need) need -= hist[b++];
+      s_need = need;
+      s_prefix = pre | ((uint64_t)b << shift);
+      s_mask = msk | ((uint64_t)255 << shift);
+    }
+    __syncthreads();
+  }
+  const uint64_t T = s_prefix;
+  const uint32_t need_eq = nb > 0 ? s_need : 0u;  // charges at exactly T that are boundary
+  // flags in index order: contiguous chunks per thread, so ties go to lower indices
+  const int chunk = (n + kBT - 1) / kBT;
+  const int j0 = min(n, t * chunk), j1 = min(n, j0 + chunk);
+  uint32_t eq = 0;
+  for (int j = j0; j < j1; ++j) eq += border_key(x[j], y[j]) == T;
+  eq_cnt[t] = eq;
+  lt_cnt[t] = 0;
+  __syncthreads();
+  for (int off = 1; off < kBT; off <<= 1) {
+    const uint32_t b = t >= off ? eq_cnt[t - off] : 0u;
+    __syncthreads();
+    eq_cnt[t] += b;
+    __syncthreads();
+  }
+  uint32_t eq_before = eq_cnt[t] - eq;
+  for (int j = j0; j < j1; ++j) {
+    const uint64_t key = border_key(x[j], y[j]);
+    int f = 0;
+    if (nb > 0) {
+      if (key < T) {
+        f = 1;
+      } else if (key == T) {
+        f = eq_before < need_eq;
+        ++eq_before;
+      }
+    }
+    flags[j] = f;
+  }
+}
+
+}  // namespace cd
+
+using namespace cd;
+
+extern "C" {
+
+int32_t border_count(int64_t n) {
+  if (n < 1) return 0;
+  const double c = cbrt((double)n);
+  const double v = floor(2.84328 * c * c - 0.530196 * c - 2.32866 + 0.5);
+  if (v < 0.0) return 0;
+  return v > (double)n ? (int32_t)n : (int32_t)v;
+}
+
+double border_sigma0(int64_t n) {
+  if (n < 1) return 1.0;
+  return 1.0 - 1.0 / (2.0 * sqrt((double)n));
+}
+
+int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_t* flags,
+                 void* stream) {
+  if (!x || !y || !flags || n < 1 || n > (1 << 26) || nb < 0 || nb > n) return CD_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_border_select, dim3(1), dim3(kBT), 0, (hipStream_t)stream, x, y, (int)n,
+                     (int)nb, flags);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -178,6 +178,9 @@ struct RelaxDev {
   double *Sx, *Sy, *Yx, *Yy;  // L-BFGS history [m][ntot]
   double* rho;             // [P][m]
   int32_t* held;           // [ntot]
+  int32_t* pin;            // [ntot] 1: boundary charge pinned to the unit circle
+  const int32_t* bflag;    // [n] caller's boundary flags (null: none)
+  double sigma;            // wall radius of the charges that are not pinned
   double* eterm;           // [ntot] per-active energy contribution of the last evaluation
   double *px, *py, *pe;    // [splits][ntot] split partials of the exact evaluation
   // mixed-path model
@@ -201,6 +204,26 @@ struct RelaxDev {
 };
 
 // ------------------------------------------------------------ setup kernels --
+// Feasible projection: a pinned charge onto the unit circle, any other charge
+// beyond its wall radius sig onto that circle.
+__device__ __forceinline__ void project_wall(double& px, double& py, int pin, double sig) {
+  const double r = sqrt(px * px + py * py);
+  if (pin) {
+    if (r > 0.0) {
+      px /= r;
+      py /= r;
+    }
+  } else if (r > sig) {
+    if (sig == 1.0) {
+      px /= r;
+      py /= r;
+    } else {
+      px *= sig / r;
+      py *= sig / r;
+    }
+  }
+}
+
 __global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
                                 const double* __restrict__ ys) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -221,11 +244,9 @@ __global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
   R.z0x[a] = R.x[i];
   R.z0y[a] = R.y[i];
   double sx = xs ? xs[a] : R.x[i], sy = ys ? ys[a] : R.y[i];
-  const double r = sqrt(sx * sx + sy * sy);
-  if (r > 1.0) {
-    sx /= r;
-    sy /= r;
-  }
+  const int pin = R.bflag ? (R.bflag[i] != 0) : 0;
+  R.pin[a] = pin;
+  project_wall(sx, sy, pin, R.sigma);
   R.zx[a] = sx;
   R.zy[a] = sy;
   R.tx[a] = sx;
@@ -763,14 +784,19 @@ __device__ void block_sum_max(double& sm, double& mx, WgRed& R) {
 }
 
 // reduced gradient component magnitude at position (px, py) with gradient g:
-// a charge on the wall whose gradient points inward is held and keeps only
-// the tangential part
-__device__ __forceinline__ bool held_rule(double px, double py, double g0, double g1) {
+// a charge on its wall (radius sig: 1 for the hard wall of Eq. 3, the
+// interior radius of the border-interior split) whose gradient points inward
+// is held and keeps only the tangential part; a pinned boundary charge is
+// always held
+__device__ __forceinline__ bool held_rule(double px, double py, double g0, double g1, int pin,
+                                          double sig) {
+  if (pin) return true;
   const double r = sqrt(px * px + py * py);
-  return r >= 1.0 - 1e-14 && (g0 * px + g1 * py) < 0.0;
+  return r >= sig * (1.0 - 1e-14) && (g0 * px + g1 * py) < 0.0;
 }
-__device__ __forceinline__ double reduced_inf(double px, double py, double g0, double g1) {
-  if (held_rule(px, py, g0, g1)) {
+__device__ __forceinline__ double reduced_inf(double px, double py, double g0, double g1, int pin,
+                                              double sig) {
+  if (held_rule(px, py, g0, g1, pin, sig)) {
     const double r = sqrt(px * px + py * py);
     const double ux = px / r, uy = py / r, gr = g0 * ux + g1 * uy;
     return fmax(fabs(g0 - gr * ux), fabs(g1 - gr * uy));
@@ -790,7 +816,7 @@ __device__ __forceinline__ void coord_grad(bool h, double px, double py, double 
 }
 
 __device__ void take_step(bool h, double px, double py, double d0, double d1, double al,
-                          double& nx, double& ny) {
+                          double& nx, double& ny, int pin, double sig) {
   if (h) {
     double sn, cs;
     sincos(al * d0, &sn, &cs);
@@ -800,11 +826,7 @@ __device__ void take_step(bool h, double px, double py, double d0, double d1, do
     nx = px + al * d0;
     ny = py + al * d1;
   }
-  const double r = sqrt(nx * nx + ny * ny);
-  if (r > 1.0) {
-    nx /= r;
-    ny /= r;
-  }
+  project_wall(nx, ny, pin, sig);
 }
 
 // Preconditioner H0 = inverse of the charge's own Hessian block (its 2x2
@@ -977,7 +999,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       R.kxx[a] = R.hkxx[a];
       R.kxy[a] = R.hkxy[a];
       R.kyy[a] = R.hkyy[a];
-      const int h = held_rule(px, py, g0, g1);
+      const int pin = R.pin[a];
+      const int h = held_rule(px, py, g0, g1, pin, R.sigma);
       if (h != R.held[a]) {
         R.held[a] = h;
         if (!s.init) {
@@ -988,7 +1011,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         }
         s_flag = 1;
       }
-      gm = fmax(gm, reduced_inf(px, py, g0, g1));
+      gm = fmax(gm, reduced_inf(px, py, g0, g1, pin, R.sigma));
     }
     const double gi = block_max(gm, red);
     __syncthreads();
@@ -1025,7 +1048,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     if (s.alpha >= 1e-10) {
       for (int a = a0 + t; a < a1; a += kUpd) {
         double nx, ny;
-        take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], s.alpha, nx, ny);
+        take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], s.alpha, nx, ny, R.pin[a],
+                  R.sigma);
         R.tx[a] = nx;
         R.ty[a] = ny;
       }
@@ -1216,7 +1240,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     R.dx[a] *= sc;
     R.dy[a] *= sc;
     double nx, ny;
-    take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], 1.0, nx, ny);
+    take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], 1.0, nx, ny, R.pin[a], R.sigma);
     R.tx[a] = nx;
     R.ty[a] = ny;
   }
@@ -1273,7 +1297,7 @@ __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double f
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   double gm = 0.0;
   for (int a = a0 + t; a < a1; a += kUpd)
-    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a]));
+    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a], R.pin[a], R.sigma));
   const double gi = block_max(gm, red);
   if (t == 0) {
     s.exact_evals++;
@@ -1301,7 +1325,7 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
   double e = 0.0, gm = 0.0;
   for (int a = a0 + t; a < a1; a += kUpd) {
     e += R.eterm[a];
-    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a]));
+    gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a], R.pin[a], R.sigma));
     if (xo) {
       xo[a] = R.zx[a];
       yo[a] = R.zy[a];
@@ -1396,6 +1420,7 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.Yy = cv.take<double>(nt * m);
   D.rho = cv.take<double>((size_t)P * m);
   D.held = cv.take<int32_t>(nt);
+  D.pin = cv.take<int32_t>(nt);
   D.eterm = cv.take<double>(nt);
   D.px = cv.take<double>(pcap);
   D.py = cv.take<double>(pcap);
@@ -1541,7 +1566,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       return CD_ERR_INVALID_ARG;
   const cd_relax_opts o = *opts;
   if (!(o.gtol > 0.0) || o.max_iter < 0 || o.halo_width < 0.0 || o.inner_tol < 0.0 ||
-      o.step0 < 0.0 || o.max_outer < 0)
+      o.step0 < 0.0 || o.max_outer < 0 || !(o.sigma >= 0.0 && o.sigma <= 1.0))
     return CD_ERR_INVALID_ARG;
   const int64_t ntot = patch_ptr[n_patches];
   if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
@@ -1565,6 +1590,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   D.c1 = 1e-4;
   D.noise_rel = 1e-14;
   D.max_iter = o.max_iter;
+  D.bflag = o.boundary;
+  D.sigma = o.sigma > 0.0 ? o.sigma : 1.0;
   g_trace = getenv("CD_RELAX_TRACE") != nullptr;
   D.eval_all = 0;
   const int max_iter_eff = o.max_iter > 0 ? o.max_iter : 1;

@@ -28,6 +28,8 @@ class RelaxOpts(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("halo_width", ctypes.c_double),
         ("step0", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("boundary", ctypes.c_void_p),
     ]
 
 
@@ -79,11 +81,12 @@ class RelaxResult:
 
 def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
-                     step0=0.0) -> RelaxResult:
+                     step0=0.0, sigma=0.0, boundary=None) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
-    the FP64 path."""
+    the FP64 path.  boundary (device int32 [n]) and sigma select the
+    border-interior split of Sec. II.B."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -97,8 +100,12 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
         ops._chk(x_start, y_start)
         if x_start.numel() != ntot:
             raise ops.CoulombError("start positions must be packed like idx")
+    if boundary is not None and (boundary.dtype != torch.int32 or boundary.numel() != n
+                                 or boundary.device != dev):
+        raise ops.CoulombError("boundary must be a device int32 tensor of length n")
     o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), int(max_outer), float(gtol),
-                  float(inner_tol), float(halo_width), float(step0))
+                  float(inner_tol), float(halo_width), float(step0), float(sigma),
+                  boundary.data_ptr() if boundary is not None else None)
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)

@@ -87,7 +87,8 @@ def test_relax_argument_errors_before_any_launch(L):
     class Opts(ctypes.Structure):
         _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                     ("max_outer", ctypes.c_int32), ("gtol", ctypes.c_double), ("inner_tol", ctypes.c_double),
-                    ("halo_width", ctypes.c_double), ("step0", ctypes.c_double)]
+                    ("halo_width", ctypes.c_double), ("step0", ctypes.c_double), ("sigma", ctypes.c_double),
+                    ("boundary", ctypes.c_void_p)]
     vp = ctypes.c_void_p
     f = L.relax_subdomains
     f.restype = ctypes.c_int
@@ -106,6 +107,8 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(Opts(1, 100, 17, 0, 1e-3, 0.0, 0.0, 0.0), big) == -1   # memory above 16
     assert call(Opts(1, 100, 8, 0, 0.0, 0.0, 0.0, 0.0), big) == -1     # gtol must be > 0
     assert call(Opts(3, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0), big) == -1    # bad precision
+    assert call(Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0, 1.5), big) == -1   # interior wall beyond the disk
+    assert call(Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0, -0.1), big) == -1  # negative interior wall
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0
