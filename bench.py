@@ -29,13 +29,15 @@ Printed: one JSON line with the driver's fields plus
 Other modes: --cycles K runs K perturb-and-relax cycles (64 kicked patches
 each, greedy commit) and prints energy versus wall time; --relax-only mixed|fp64
 times one relax call on the 256 patches of workload 4; --defect-only mixed|fp64
-runs one defect-targeted cycle; --copy-probe runs a plain device copy of known
-size (to calibrate HBM byte counters).
+runs one defect-targeted cycle; --border-sweep N runs one such cycle per
+boundary population around Eq. 4 under the border-interior split (Sec. II.B);
+--copy-probe runs a plain device copy of known size (to calibrate HBM byte
+counters).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
                        [--no-relax] [--tune] [--cycles K --cycle-n N --cycle-precision P]
                        [--relax-only mixed|fp64] [--defect-only mixed|fp64 --defect-T T
-                       --defect-kappa K] [--no-defect] [--copy-probe]
+                       --defect-kappa K] [--no-defect] [--border-sweep N] [--copy-probe]
 """
 import argparse
 import ctypes
@@ -309,6 +311,34 @@ def defect_cycle_run(dev, n, kappa, precision, T=1000, log=None):
     return out
 
 
+def border_sweep(dev, n, T, precision, offsets=(-2, -1, 0, 1, 2)):
+    """Table-I-style sweep: one defect-targeted cycle per boundary population
+    N_b = Eq. 4's value + offset (border-interior split, sigma ramped from
+    Eq. 5's value to 1 over the cycle), and one under the hard wall, all from
+    the same start (lattice workload 5 at this N)."""
+    import torch
+    from paper_2609_24722_amd import border as B
+    from paper_2609_24722_amd import workloads as W
+    from paper_2609_24722_amd.cycle import defect_cycle
+    x, y = W.workload(5, n)
+    nb0 = B.boundary_count(n)
+    rows = []
+    for off in (None,) + tuple(offsets):
+        xt = torch.tensor(x, device=dev)
+        yt = torch.tensor(y, device=dev)
+        nb = None if off is None else nb0 + off
+        out = defect_cycle(xt, yt, T=T, precision=precision, border_nb=nb)
+        out.pop("batch_records")
+        row = {"n": n, "N_b": nb, "N_core": None if nb is None else n - nb, "E_start": out["E_start"],
+               "E_end": out["E_end"], "wall_s": out["wall_s"], "batches": out["batches"],
+               "committed": out["committed"], "sigma_start": out["sigma_start"],
+               "tracked_minus_fresh_rel": (out["tracked_energy"] - out["E_end"]) / out["E_end"]}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps({"border_sweep": rows, "N_b_eq4": nb0, "T": T,
+                      "precision": "mixed" if precision else "fp64"}), flush=True)
+
+
 def traffic_from_profiles():
     """HBM bytes per launch of the pair kernel from the committed counter
     summary, if it matches the current kernel build; else None."""
@@ -347,6 +377,9 @@ def main():
                     help="run one defect-targeted cycle (N=--n, T=--defect-T) and exit")
     ap.add_argument("--defect-T", type=int, default=1000)
     ap.add_argument("--defect-kappa", type=float, default=-1.0)
+    ap.add_argument("--border-sweep", type=int, default=0, metavar="N",
+                    help="one defect-targeted cycle per N_b around Eq. 4 (border-interior split) at N "
+                         "charges, plus the hard wall, and exit")
     ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
@@ -367,6 +400,9 @@ def main():
         return
     if args.relax_only:
         relax_only(dev, MIXED if args.relax_only == "mixed" else FP64)
+        return
+    if args.border_sweep:
+        border_sweep(dev, args.border_sweep, args.defect_T, MIXED)
         return
     if args.defect_only:
         log = lambda r: print(json.dumps(r), flush=True)

@@ -267,6 +267,15 @@ double border_sigma0(int64_t n);
 int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_t* flags,
                  void* stream);
 
+/* Projection onto the split's feasible set, in place on x, y (device [n]):
+ * a charge with flags[i] != 0 onto the unit circle (x / r), any other charge
+ * with r > sigma onto the circle of radius sigma (x * (sigma / r)), with
+ * r = sqrt((x*x) + (y*y)) and each operation rounded once in FP64.  flags:
+ * device int32 [n] or NULL (no boundary charges); 0 < sigma <= 1.  Does not
+ * synchronise. */
+int border_project(double* x, double* y, int64_t n, const int32_t* flags, double sigma,
+                   void* stream);
+
 /* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
  * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE
  * of relax_subdomains) is negative are visited in increasing order of it

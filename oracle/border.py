@@ -11,6 +11,9 @@ imports the GPU library.
 * ``border_split``   -- which charges are boundary charges: the N_b charges
   farthest from the centre, by x*x + y*y rounded once per operation in FP64,
   ties to the lower index.
+* ``border_project`` -- the feasible point nearest along the ray: boundary
+  charges onto the unit circle (x / r), others beyond sigma onto radius sigma
+  (x * (sigma / r)).
 
 The relaxation under this constraint is ``relax(..., pin=..., sigma=...)`` of
 this package (oracle.c: boundary charges pinned to the unit circle, the others
@@ -50,3 +53,19 @@ def border_split(x, y, nb: int) -> np.ndarray:
     flags = np.zeros(x.size, dtype=np.int32)
     flags[order[:nb]] = 1
     return flags
+
+
+def border_project(x, y, flags, sigma: float):
+    """Projected copies of (x, y) (see the module docstring)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    y = np.array(y, dtype=np.float64, copy=True)
+    r = np.sqrt(x * x + y * y)
+    fl = np.zeros(x.size, bool) if flags is None else np.asarray(flags) != 0
+    on = fl & (r > 0.0)
+    x[on] = x[on] / r[on]
+    y[on] = y[on] / r[on]
+    out = ~fl & (r > sigma)
+    f = sigma / r[out]
+    x[out] = x[out] * f
+    y[out] = y[out] * f
+    return x, y

@@ -24,6 +24,9 @@ def _lib():
         L.border_split.restype = ctypes.c_int
         L.border_split.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p]
+        L.border_project.restype = ctypes.c_int
+        L.border_project.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_double, ctypes.c_void_p]
         L._border_bound = True
     return L
 
@@ -52,3 +55,14 @@ def border_split(x, y, nb: int):
     ops.check(_lib().border_split(x.data_ptr(), y.data_ptr(), n, int(nb), flags.data_ptr(),
                                   ops.stream_ptr(dev)), "border_split")
     return flags
+
+
+def border_project(x, y, flags, sigma: float) -> None:
+    """Project (x, y) in place: flagged charges onto the unit circle, the
+    others into radius sigma."""
+    dev = ops._chk(x, y)
+    if flags is not None and (flags.dtype != torch.int32 or flags.numel() != x.numel() or flags.device != dev):
+        raise ops.CoulombError("flags must be a device int32 tensor of length n")
+    ops.check(_lib().border_project(x.data_ptr(), y.data_ptr(), x.numel(),
+                                    flags.data_ptr() if flags is not None else None, float(sigma),
+                                    ops.stream_ptr(dev)), "border_project")

@@ -1,6 +1,7 @@
 // Border-interior split of the charges (paper Sec. II.B): the boundary
-// population of Eq. 4, the initial interior radius of Eq. 5, and which
-// charges are boundary charges (the N_b farthest from the centre).
+// population of Eq. 4, the initial interior radius of Eq. 5, which charges
+// are boundary charges (the N_b farthest from the centre), and the
+// projection of a configuration onto the split's feasible set.
 //
 // k_border_select: one 1024-thread workgroup.  The key of charge i is the
 // bit pattern of r2 = (x*x) + (y*y) (separately rounded, non-negative, so it
@@ -88,6 +89,30 @@ __global__ __launch_bounds__(kBT) void k_border_select(const double* __restrict_
   }
 }
 
+// In-place projection onto the split's feasible set: a boundary charge onto
+// the unit circle (x / r), any other charge beyond sigma onto the circle of
+// radius sigma (x * (sigma / r)); every operation rounded once in FP64.
+#pragma clang fp contract(off)
+__global__ void k_border_project(double* __restrict__ x, double* __restrict__ y, int n,
+                                 const int32_t* __restrict__ flags, double sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = x[i], py = y[i];
+  const double a = px * px, b = py * py;
+  const double r = sqrt(a + b);
+  if (flags && flags[i]) {
+    if (r > 0.0) {
+      x[i] = px / r;
+      y[i] = py / r;
+    }
+  } else if (r > sigma) {
+    const double f = sigma / r;
+    x[i] = px * f;
+    y[i] = py * f;
+  }
+}
+#pragma clang fp contract(on)
+
 }  // namespace cd
 
 using namespace cd;
@@ -112,6 +137,15 @@ int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_
   if (!x || !y || !flags || n < 1 || n > (1 << 26) || nb < 0 || nb > n) return CD_ERR_INVALID_ARG;
   hipLaunchKernelGGL(k_border_select, dim3(1), dim3(kBT), 0, (hipStream_t)stream, x, y, (int)n,
                      (int)nb, flags);
+  return hip_status(hipGetLastError());
+}
+
+int border_project(double* x, double* y, int64_t n, const int32_t* flags, double sigma,
+                   void* stream) {
+  if (!x || !y || n < 1 || n > (1 << 26) || !(sigma > 0.0 && sigma <= 1.0))
+    return CD_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_border_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, x, y, (int)n, flags, sigma);
   return hip_status(hipGetLastError());
 }
 

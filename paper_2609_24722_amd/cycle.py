@@ -27,7 +27,7 @@ import time
 import numpy as np
 import torch
 
-from . import FP64, MIXED, ops, relax as R, workloads as W, zones as Z
+from . import FP64, MIXED, border as B, ops, relax as R, workloads as W, zones as Z
 
 
 def perturb_relax_cycles(x, y, cycles: int, n_patches: int = 64, size_lo: int = 200,
@@ -65,7 +65,8 @@ def perturb_relax_cycles(x, y, cycles: int, n_patches: int = 64, size_lo: int = 
 
 def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_defect: float = 0.8,
                  n_lo: int = 200, n_hi: int = 4000, period: int = 250, gap_h: float = 2.0,
-                 seed: int = 1006, precision: int = MIXED, gtol: float = 1e-3, log=None, inspect=None):
+                 seed: int = 1006, precision: int = MIXED, gtol: float = 1e-3, log=None, inspect=None,
+                 border_nb: int | None = None, sigma_start: float | None = None, sigma_end: float = 1.0):
     """One defect-targeted cycle of T subdomain optimisations (Sec. II.C).
     x, y: device float64 tensors, updated in place.
 
@@ -83,6 +84,12 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
       side by side against that snapshot, committed greedily with exact
       energy changes.
 
+    * With border_nb, the border-interior split of Sec. II.B: the border_nb
+      charges farthest from the centre are pinned to the unit circle, the
+      others confined within sigma, which rises linearly over the cycle's
+      batches from sigma_start (default Eq. 5's value) to sigma_end; the
+      configuration is projected onto the split at the start.
+
     Returns a summary dict (energies, counts, wall time, per-batch records).
     inspect(b, sel, cx, cy, rz, ptr, idx), if given, sees each batch's zones
     (host arrays of the zone indices and all T centres and radii, the packed
@@ -94,6 +101,12 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
     r_hi = float(np.sqrt(n_hi / n))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    flags = None
+    s0 = 1.0
+    if border_nb is not None:
+        s0 = B.sigma0(n) if sigma_start is None else float(sigma_start)
+        flags = B.border_split(x, y, int(border_nb))
+        B.border_project(x, y, flags, s0)
     E0, e = ops.energy(x, y, FP64, local=True)
     draws = torch.tensor(W.zone_draws(T, seed), device=dev)
     z = Z.defect_zones(x, y, e, draws, kappa, p_defect, r_lo, r_hi, 0, period)
@@ -124,7 +137,10 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
             ptr = R.offsets(sizes[keep])
         if inspect is not None:
             inspect(b, sel[keep], cx, cy, rz, ptr, idx)
-        res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol)
+        sig = 0.0
+        if flags is not None:
+            sig = s0 + (sigma_end - s0) * (b / max(1, nb - 1))
+        res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol, sigma=sig, boundary=flags)
         com, dc = R.commit_patches(x, y, ptr, idx, res.x, res.y, res.dE.cpu().numpy())
         tracked += float(dc[com == 1].sum())
         st = np.bincount(res.status.cpu().numpy(), minlength=4)[:4]
@@ -140,7 +156,8 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
     E1 = float(ops.energy(x, y, FP64).item())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"T": T, "batches": nb, "zones_relaxed": relaxed, "committed": committed,
+    return {"T": T, "border_nb": border_nb, "sigma_start": s0 if flags is not None else None,
+            "sigma_end": sigma_end if flags is not None else None, "batches": nb, "zones_relaxed": relaxed, "committed": committed,
             "actives_total": actives, "defects": int(stats[3]), "mu": float(stats[0]),
             "sigma_e": float(stats[1]), "threshold": float(stats[2]),
             "defect_centres": int((ci >= 0).sum()), "E_start": E0, "E_end": E1, "tracked_energy": tracked,

@@ -140,3 +140,44 @@ def test_relax_bi_same_basin(dev):
             d = np.hypot(r.x.cpu().numpy()[sl] - xo, r.y.cpu().numpy()[sl] - yo).max()
             assert d <= 1e-3 * h
     assert sum(int(flags[idx_np[ptr[p]:ptr[p + 1]]].sum()) for p in range(2)) > 0
+
+
+def test_border_project_bit_exact(dev):
+    x, y = W.uniform_disk(5000, 41)
+    x[0], y[0] = 0.0, 0.0  # a boundary charge at the centre stays
+    flags = OB.border_split(x, y, 400)
+    flags[0] = 1
+    for sigma in (0.3, 0.95, 1.0):
+        xt, yt = t(x, dev), t(y, dev)
+        B.border_project(xt, yt, t(flags, dev, torch.int32), sigma)
+        px, py = OB.border_project(x, y, flags, sigma)
+        assert np.array_equal(xt.cpu().numpy(), px) and np.array_equal(yt.cpu().numpy(), py)
+        xt, yt = t(x, dev), t(y, dev)
+        B.border_project(xt, yt, None, sigma)
+        px, py = OB.border_project(x, y, None, sigma)
+        assert np.array_equal(xt.cpu().numpy(), px) and np.array_equal(yt.cpu().numpy(), py)
+
+
+def test_defect_cycle_border_interior_small(dev):
+    """A small defect-targeted cycle under the split with the sigma ramp:
+    boundary charges stay on the circle, interior ones within the final
+    sigma, the energy falls, and the tracked energy equals a fresh oracle
+    evaluation."""
+    from paper_2609_24722_amd import cycle
+    n = 6000
+    x, y = W.warped_lattice(n, 0.1, 1107)
+    xt, yt = t(x, dev), t(y, dev)
+    nb = B.boundary_count(n)
+    flags = OB.border_split(x, y, nb)
+    out = cycle.defect_cycle(xt, yt, T=96, cap=32, n_lo=50, n_hi=400, period=24, seed=1209, precision=MIXED,
+                             border_nb=nb)
+    xs, ys = xt.cpu().numpy(), yt.cpu().numpy()
+    r = np.hypot(xs, ys)
+    print(f"[bi-cycle] nb={nb} batches={out['batches']} committed={out['committed']} "
+          f"E {out['E_start']:.10e} -> {out['E_end']:.10e}", flush=True)
+    assert out["E_end"] < out["E_start"]
+    assert abs(out["tracked_energy"] - out["E_end"]) <= 1e-12 * out["E_end"]
+    assert abs(out["E_end"] - O.energy(xs, ys)) <= 1e-13 * out["E_end"]
+    assert np.all(np.abs(r[flags == 1] - 1.0) <= 1e-15)
+    assert np.all(r[flags == 0] <= 1.0 + 1e-15)
+    assert out["committed"] >= 48 and out["relax_status"][0] >= 90

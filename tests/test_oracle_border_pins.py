@@ -136,3 +136,19 @@ def test_relax_bi_kkt_endpoint():
         worst = max(worst, abs(tx), abs(ty))
     assert worst <= 1e-9
     assert ((r >= sigma * (1 - 1e-14)) & (pin == 0)).sum() > 0  # the interior wall is active
+
+
+def test_border_project_definition():
+    """Projection: boundary charges land on the unit circle along their ray,
+    interior charges beyond sigma on the sigma circle, the rest unchanged
+    (dyadic points make every value exact)."""
+    x = np.array([0.5, 0.0, 0.75, 0.25, -0.5])
+    y = np.array([0.0, 0.5, 0.0, 0.0, 0.0])
+    flags = np.array([1, 1, 0, 0, 0])
+    px, py = B.border_project(x, y, flags, 0.5)
+    assert px.tolist() == [1.0, 0.0, 0.5, 0.25, -0.5] and py.tolist() == [0.0, 1.0, 0.0, 0.0, 0.0]
+    x, y = W.uniform_disk(500, 3)
+    px, py = B.border_project(x, y, None, 0.7)
+    r0, r1 = np.hypot(x, y), np.hypot(px, py)
+    assert np.all(r1 <= 0.7 * (1 + 1e-15)) and np.array_equal(px[r0 <= 0.7], x[r0 <= 0.7])
+    assert np.allclose(np.arctan2(py, px), np.arctan2(y, x), atol=1e-15)
