@@ -72,6 +72,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.orc_energy.restype = ctypes.c_double
         L.orc_energy.argtypes = [ctypes.c_int64, _D, _D, _D]
+        L.orc_riesz.restype = ctypes.c_double
+        L.orc_riesz.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D]
         L.orc_forces.restype = None
         L.orc_forces.argtypes = [ctypes.c_int64, _D, _D, _D, _D]
         L.orc_hvp.restype = None
@@ -141,6 +143,20 @@ def forces(x, y):
     fy = np.empty(x.size)
     lib().orc_forces(x.size, px, py, fx.ctypes.data_as(_D), fy.ctypes.data_as(_D))
     return fx, fy
+
+
+def riesz(x, y, s: float, forces: bool = True):
+    """Riesz-s energy sum_{i<j} r^-s and, with forces, F_i = sum_j s (r_i - r_j)
+    r^(-s-2).  Returns E or (E, fx, fy)."""
+    x, px = _d(x)
+    y, py = _d(y)
+    n = x.size
+    if not forces:
+        return lib().orc_riesz(n, px, py, float(s), None, None)
+    fx = np.empty(n)
+    fy = np.empty(n)
+    E = lib().orc_riesz(n, px, py, float(s), fx.ctypes.data_as(_D), fy.ctypes.data_as(_D))
+    return E, fx, fy
 
 
 def hvp(x, y, vx, vy):

@@ -29,6 +29,7 @@
  *   orc_esub_delta   E_sub(moved) - E_sub(snapshot) as a sum over changed pairs
  *                    of the change of 1/r, formed without cancellation.
  *   orc_esub_hvp     Hessian-vector product of E_sub over the active coordinates.
+ *   orc_riesz        Riesz-s energy and forces (1/r^s pairs).
  *   orc_reduce_grad  hard-wall (Eq. 3) KKT reduction of the gradient.
  *   orc_relax        local relaxation of one subdomain (Sec. II.C step 4):
  *                    L-BFGS on free and wall-held coordinates, then
@@ -125,6 +126,42 @@ void orc_forces(int64_t n, const double *x, const double *y, double *fx, double 
     fx[i] = nval(&ax);
     fy[i] = nval(&ay);
   }
+}
+
+/* ----------------------------------------------------------------- Riesz -- */
+/* The Riesz-s generalisation of Eq. 2 (the paper states its result in Riesz
+ * terms): E = sum_{i<j} r_ij^(-s) and F_i = -dE/dr_i =
+ * sum_{j!=i} s (r_i - r_j) r_ij^(-s-2).  Pair terms from pow(); sums are
+ * Neumaier-compensated, rows in index order.  fx, fy may be NULL. */
+double orc_riesz(int64_t n, const double *x, const double *y, double s, double *fx, double *fy) {
+  double *rs = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *rc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    nacc e = {0.0, 0.0}, ax = {0.0, 0.0}, ay = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dx = x[i] - x[j], dy = y[i] - y[j];
+      double r2 = dx * dx + dy * dy;
+      double p = pow(r2, -0.5 * s); /* r^-s */
+      if (j > i) nadd(&e, p);
+      double w = s * p / r2;
+      nadd(&ax, dx * w);
+      nadd(&ay, dy * w);
+    }
+    rs[i] = e.s;
+    rc[i] = e.c;
+    if (fx) fx[i] = nval(&ax);
+    if (fy) fy[i] = nval(&ay);
+  }
+  nacc t = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) {
+    nadd(&t, rs[i]);
+    nadd(&t, rc[i]);
+  }
+  free(rs);
+  free(rc);
+  return nval(&t);
 }
 
 /* The same sums for a subset of rows only (sampled checks at large N):
