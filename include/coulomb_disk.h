@@ -84,6 +84,17 @@ int coulomb_energy(const double* x, const double* y, int64_t n, int precision,
 int coulomb_forces(const double* x, const double* y, int64_t n, int precision, double* fx,
                    double* fy, double* e_total, void* ws, size_t ws_bytes, void* stream);
 
+/* Riesz-s generalisation of Eq. 2 (the paper states its result in Riesz
+ * terms, Sec. III.E): *e_total = sum_{i<j} r_ij^(-s) (nullable) and
+ * F_i = -dE/dr_i = sum_{j!=i} s (r_i - r_j) r_ij^(-s-2): fx[n], fy[n].
+ * s = 1 is the Coulomb case of coulomb_forces.  0 < s <= 6 on CD_MIXED
+ * (FP32 pair terms 2^((-s/2-1) log2 r^2) from the hardware log2/exp2, so
+ * close pairs must keep r^(-s-2) within FP32 range), 0 < s <= 64 on CD_FP64
+ * (pow).  ws: coulomb_workspace_bytes(CD_OP_FORCES, n, 0, 0, precision). */
+int coulomb_riesz(const double* x, const double* y, int64_t n, double s, int precision,
+                  double* fx, double* fy, double* e_total, void* ws, size_t ws_bytes,
+                  void* stream);
+
 /* Hessian-vector product of Eq. 2's energy: (H v)_i = sum_{j!=i} K(d_ij)
  * (v_i - v_j), K(d) = (3 d d^T - |d|^2 I)/|d|^5, d_ij = r_i - r_j.
  * vx, vy, hx, hy: [n].  CD_MIXED: components of v must stay below 1e8 in

@@ -24,7 +24,9 @@ size_t sort_scratch_elems(int n);
 int morton_order(const double* x, const double* y, int n, uint32_t* ka, uint32_t* kb,
                  int32_t* va, uint32_t* hist, int32_t* perm, hipStream_t st);
 
-enum Mode { kEnergy = 0, kForces = 1, kHvp = 2 };
+// kRiesz: energy and forces of the Riesz-s generalisation (1/r^s pairs);
+// it takes the force path everywhere except the pair arithmetic.
+enum Mode { kEnergy = 0, kForces = 1, kHvp = 2, kRiesz = 3 };
 
 // ------------------------------------------------------------------ staging --
 // Sorted, padded copies (xs[s] = x[perm[s]] for s < n, pads beyond; v only
@@ -124,6 +126,7 @@ struct SymArgs {
   double* dp1;
   double* dep;  // their energy, per super-block [ns]
   double diag_scale;  // weight of the ordered within-block energy sum
+  float rz_e, rz_s;   // kRiesz: -(s/2) - 1 and s
 };
 
 // One charge per lane, relative to a reference point: coordinates (hi, lo)
@@ -183,9 +186,23 @@ template <int MODE, bool LOCAL>
 struct PairOps {
   // one pair: d = r_j - r_i (FP32), w = v_j - v_i (HVP only)
   // i-side accumulators a0,a1,a2; j-side accumulators b0,b1 (already aligned)
+  // re, rs: the Riesz exponents (kRiesz only)
   __device__ __forceinline__ static void apply(float dx, float dy, float wx, float wy, float& a0,
-                                               float& a1, float& a2, float& b0, float& b1) {
+                                               float& a1, float& a2, float& b0, float& b1,
+                                               float re, float rs) {
     const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+    if (MODE == kRiesz) {
+      // q = r^(-s-2) = 2^(re log2 r2); the energy term is q r2 = r^-s.  A pad
+      // gives r2 = +inf and q = exactly 0; the clamp keeps 0 * inf out.
+      const float q = __builtin_amdgcn_exp2f(re * __builtin_amdgcn_logf(r2));
+      a2 = __builtin_fmaf(q, fminf(r2, 1e30f), a2);
+      const float c = rs * q;
+      a0 = __builtin_fmaf(-dx, c, a0);
+      a1 = __builtin_fmaf(-dy, c, a1);
+      b0 = __builtin_fmaf(dx, c, b0);
+      b1 = __builtin_fmaf(dy, c, b1);
+      return;
+    }
     const float inv = __builtin_amdgcn_rsqf(r2);
     if (MODE == kEnergy) {
       a2 += inv;
@@ -264,14 +281,15 @@ __device__ __forceinline__ void rotate_rows(Side& j, int src) {
 template <int MODE, bool LOCAL, bool NEAR, bool ONESIDED>
 struct BlockPair {
   __device__ __forceinline__ static void run(const Side& i, Side j, float& a0, float& a1,
-                                             float& a2, float& b0, float& b1, int lane) {
+                                             float& a2, float& b0, float& b1, int lane,
+                                             float re = 0.f, float rs = 0.f) {
     const int src = (lane + 16) & 63;
     float dx, dy, wx, wy;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       if (!(ONESIDED && p == 0)) {  // the self pair of a diagonal block is skipped
         diff<MODE, NEAR, 0>(i, j, dx, dy, wx, wy);
-        PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1);
+        PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1, re, rs);
       }
 #define CD_SYM_STEP(K)                                                  \
   {                                                                     \
@@ -280,7 +298,7 @@ struct BlockPair {
       b0 = row_ror<1>(b0);                                              \
       if (MODE != kEnergy) b1 = row_ror<1>(b1);                         \
     }                                                                   \
-    PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1);    \
+    PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, a0, a1, a2, b0, b1, re, rs); \
   }
       CD_SYM_STEP(1) CD_SYM_STEP(2) CD_SYM_STEP(3) CD_SYM_STEP(4) CD_SYM_STEP(5)
       CD_SYM_STEP(6) CD_SYM_STEP(7) CD_SYM_STEP(8) CD_SYM_STEP(9) CD_SYM_STEP(10)
@@ -304,7 +322,7 @@ template <int MODE, bool LOCAL, bool NEAR>
 struct BlockPairN {
   __device__ __forceinline__ static void run(const Side (&u)[NI], Side (&j)[NI],
                                              float (&acc)[NI][3], float& b0, float& b1,
-                                             int lane) {
+                                             int lane, float re = 0.f, float rs = 0.f) {
     const int src = (lane + 16) & 63;
     float dx, dy, wx, wy;
 #pragma unroll
@@ -312,7 +330,8 @@ struct BlockPairN {
 #pragma unroll
       for (int q = 0; q < NI; ++q) {
         diff<MODE, NEAR, 0>(u[q], j[q], dx, dy, wx, wy);
-        PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1);
+        PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1, re,
+                                    rs);
       }
 #define CD_SYM_STEPN(K)                                                                     \
   {                                                                                         \
@@ -320,7 +339,8 @@ struct BlockPairN {
     if (MODE != kEnergy) b1 = row_ror<1>(b1);                                               \
     _Pragma("unroll") for (int q = 0; q < NI; ++q) {                                        \
       diff<MODE, NEAR, K>(u[q], j[q], dx, dy, wx, wy);                                      \
-      PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1); \
+      PairOps<MODE, LOCAL>::apply(dx, dy, wx, wy, acc[q][0], acc[q][1], acc[q][2], b0, b1, re, \
+                                  rs);                                                      \
     }                                                                                       \
   }
       CD_SYM_STEPN(1) CD_SYM_STEPN(2) CD_SYM_STEPN(3) CD_SYM_STEPN(4) CD_SYM_STEPN(5)
@@ -400,12 +420,12 @@ __device__ __forceinline__ void sym_diag(const SymArgs& a, int I, int w, int lan
         load_side<MODE>(a, (size_t)I * SB + q * kBlk + lane, ccx, ccy, rvx, rvy, true);
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f;
     if (q == r) {
-      BlockPair<MODE, false, true, true>::run(sq, sq, a0, a1, a2, b0, b1, lane);
+      BlockPair<MODE, false, true, true>::run(sq, sq, a0, a1, a2, b0, b1, lane, a.rz_e, a.rz_s);
       b0 = b1 = 0.f;
     } else {
       const Side sr =
           load_side<MODE>(a, (size_t)I * SB + r * kBlk + lane, ccx, ccy, rvx, rvy, true);
-      BlockPair<MODE, LOCAL, true, false>::run(sq, sr, a0, a1, a2, b0, b1, lane);
+      BlockPair<MODE, LOCAL, true, false>::run(sq, sr, a0, a1, a2, b0, b1, lane, a.rz_e, a.rz_s);
     }
     const float dscale = q == r ? (float)a.diag_scale : 1.f;  // 0.5 or 1: exact in FP32
     part[p][0][0][lane] = a0;
@@ -566,9 +586,9 @@ __global__ __launch_bounds__(64 * kSymWaves) __attribute__((amdgpu_waves_per_eu(
       for (int q = 0; q < NI; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.f;
       float b0 = 0.f, b1 = 0.f;
       if (near)
-        BlockPairN<MODE, LOCAL, true>::run(u, j, acc, b0, b1, lane);
+        BlockPairN<MODE, LOCAL, true>::run(u, j, acc, b0, b1, lane, a.rz_e, a.rz_s);
       else
-        BlockPairN<MODE, LOCAL, false>::run(u, j, acc, b0, b1, lane);
+        BlockPairN<MODE, LOCAL, false>::run(u, j, acc, b0, b1, lane, a.rz_e, a.rz_s);
 #pragma unroll
       for (int q = 0; q < NI; ++q) {
         U[q][0] += (double)acc[q][0];
@@ -733,6 +753,7 @@ struct OneArgs {
   const double* vxs;
   const double* vys;
   int n, nb, npad, jb;  // jb = j blocks per split
+  double rs;            // kRiesz: the exponent s
   double* p0;        // [splits][npad]
   double* p1;
   double* p2;
@@ -744,11 +765,22 @@ __device__ __forceinline__ void one64_block(const double* __restrict__ xb,
                                             const double* __restrict__ vxb,
                                             const double* __restrict__ vyb, int jn, double xi,
                                             double yi, double vxi, double vyi, int lane,
-                                            double& A0, double& A1, double& A2) {
+                                            double& A0, double& A1, double& A2, double rs) {
 #pragma unroll 4
   for (int jj = 0; jj < jn; ++jj) {
     const double dx = xi - xb[jj], dy = yi - yb[jj];
     const double r2 = __builtin_fma(dx, dx, dy * dy);
+    if (MODE == kRiesz) {
+      // r^-s by pow; the self pair is taken at r2 = 1 and zeroed
+      const bool self = SELF && jj == lane;
+      const double q2 = self ? 1.0 : r2;
+      const double p = self ? 0.0 : pow(q2, -0.5 * rs);
+      const double w = rs * p / q2;
+      A2 += p;
+      A0 = __builtin_fma(dx, w, A0);
+      A1 = __builtin_fma(dy, w, A1);
+      continue;
+    }
     double inv = rsqrt64(r2);
     if (SELF) inv = (jj == lane) ? 0.0 : inv;
     if (MODE == kEnergy) {
@@ -788,9 +820,9 @@ __global__ __launch_bounds__(256) void k_one64(OneArgs a) {
     const double* vyb = MODE == kHvp ? a.vys + (size_t)J * kBlk : nullptr;
     const int jn = min(kBlk, a.n - J * kBlk);  // real charges only; pads never enter
     if (J == I)
-      one64_block<MODE, true>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2);
+      one64_block<MODE, true>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs);
     else
-      one64_block<MODE, false>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2);
+      one64_block<MODE, false>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs);
   }
   const size_t k = (size_t)blockIdx.y * a.npad + si;
   if (MODE == kEnergy) {
@@ -798,7 +830,7 @@ __global__ __launch_bounds__(256) void k_one64(OneArgs a) {
   } else {
     a.p0[k] = A0;
     a.p1[k] = A1;
-    if (MODE == kForces) a.p2[k] = A2;
+    if (MODE == kForces || MODE == kRiesz) a.p2[k] = A2;
   }
 }
 
@@ -826,7 +858,7 @@ __global__ __launch_bounds__(256) void k_one64_reduce(OneReduceArgs a) {
       } else {
         v0 += a.p0[q];
         v1 += a.p1[q];
-        if (MODE == kForces) ve += a.p2[q];
+        if (MODE == kForces || MODE == kRiesz) ve += a.p2[q];
       }
     }
     ve *= 0.5;  // ordered pairs: e_i = 1/2 sum_{j != i} 1/r_ij
@@ -1030,8 +1062,11 @@ static void mark(hipEvent_t ev, hipStream_t st) {
 // Symmetric pass in batches of chunks, each followed by its reduction, and
 // (forces, energy) the total energy.
 template <int MODE, bool LOCAL>
-static void run_sym(const Plan& P, hipStream_t st, double* out0, double* out1, double* e_total) {
+static void run_sym(const Plan& P, hipStream_t st, double* out0, double* out1, double* e_total,
+                    double riesz_s = 0.0) {
   SymArgs a;
+  a.rz_e = (float)(-0.5 * riesz_s - 1.0);
+  a.rz_s = (float)riesz_s;
   a.xs = P.xs;
   a.ys = P.ys;
   a.vxs = P.vxs;
@@ -1111,8 +1146,10 @@ static void run_sym(const Plan& P, hipStream_t st, double* out0, double* out1, d
 }
 
 template <int MODE>
-static void run_one64(const Plan& P, hipStream_t st, double* out0, double* out1) {
+static void run_one64(const Plan& P, hipStream_t st, double* out0, double* out1,
+                      double riesz_s = 0.0) {
   OneArgs a;
+  a.rs = riesz_s;
   a.xs = P.xs;
   a.ys = P.ys;
   a.vxs = P.vxs;
@@ -1257,6 +1294,24 @@ static int forces_impl(const double* x, const double* y, int64_t n, int precisio
   return hip_status(hipGetLastError());
 }
 
+static int riesz_impl(const double* x, const double* y, int64_t n, double rs, int precision,
+                      double* fx, double* fy, double* e_total, void* ws, size_t ws_bytes,
+                      hipStream_t st) {
+  if (!x || !y || !fx || !fy) return CD_ERR_INVALID_ARG;
+  if (!(rs > 0.0) || rs > (precision == CD_MIXED ? 6.0 : 64.0)) return CD_ERR_INVALID_ARG;
+  Plan P;
+  int rc = check_ws(CD_OP_FORCES, n, precision, ws, ws_bytes, P, -1);
+  if (rc) return rc;
+  if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
+  if (precision == CD_MIXED) {
+    run_sym<kRiesz, false>(P, st, fx, fy, e_total, rs);
+  } else {
+    run_one64<kRiesz>(P, st, fx, fy, rs);
+    if (e_total) sum_blocks(P.eblk, P.nred, e_total, st);
+  }
+  return hip_status(hipGetLastError());
+}
+
 static int hvp_impl(const double* x, const double* y, const double* vx, const double* vy,
                     int64_t n, int precision, double* hx, double* hy, void* ws, size_t ws_bytes,
                     hipStream_t st, int shape) {
@@ -1279,6 +1334,12 @@ int coulomb_energy(const double* x, const double* y, int64_t n, int precision, d
 int coulomb_forces(const double* x, const double* y, int64_t n, int precision, double* fx,
                    double* fy, double* e_total, void* ws, size_t ws_bytes, void* stream) {
   return forces_impl(x, y, n, precision, fx, fy, e_total, ws, ws_bytes, (hipStream_t)stream, -1);
+}
+
+int coulomb_riesz(const double* x, const double* y, int64_t n, double s, int precision,
+                  double* fx, double* fy, double* e_total, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return riesz_impl(x, y, n, s, precision, fx, fy, e_total, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int coulomb_hvp(const double* x, const double* y, const double* vx, const double* vy, int64_t n,

@@ -123,6 +123,26 @@ def forces(x, y, precision: int = MIXED, with_energy: bool = True):
     return fx, fy, E
 
 
+def riesz(x, y, s: float, precision: int = MIXED, with_energy: bool = True):
+    """Riesz-s energy sum_{i<j} r^-s and forces F_i = sum_j s (r_i - r_j) r^(-s-2);
+    returns (fx, fy, E or None)."""
+    dev = _chk(x, y)
+    n = x.numel()
+    L = lib()
+    if not getattr(L, "_riesz_bound", False):
+        L.coulomb_riesz.restype = ctypes.c_int
+        L.coulomb_riesz.argtypes = [_vp, _vp, _i64, ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
+        L._riesz_bound = True
+    fx = torch.empty(n, dtype=torch.float64, device=dev)
+    fy = torch.empty(n, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev) if with_energy else None
+    ws, nb = workspace(OP_FORCES, n, precision, dev)
+    check(L.coulomb_riesz(x.data_ptr(), y.data_ptr(), n, float(s), precision, fx.data_ptr(), fy.data_ptr(),
+                          E.data_ptr() if with_energy else None, ws.data_ptr(), nb, stream_ptr(dev)),
+          "coulomb_riesz")
+    return fx, fy, E
+
+
 def hvp(x, y, vx, vy, precision: int = MIXED):
     """(H v)_i = sum_{j!=i} K(d_ij)(v_i - v_j); returns (hx, hy)."""
     dev = _chk(x, y, vx, vy)
