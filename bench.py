@@ -11,7 +11,8 @@ Printed: one JSON line with the driver's fields plus
                 (algorithmic flops: 13 per ordered pair; kernel time from HIP
                 events recorded around that kernel on its stream);
   cpu_baseline  the CPU oracle on a bounded sample of rows of the same input;
-  extra         FP64 energy+forces, HVP (both precisions) and energy-only rates.
+  extra         FP64 energy+forces, HVP (both precisions), energy-only rates and the
+                Riesz-s generalisation (s = 2, 3 mixed; s = 2 FP64).
 
   relax         the batched subdomain relax of 256 patches (sizes U{200..5000})
                 on the same configuration, mixed path, seconds per batch ("cycle");
@@ -53,6 +54,7 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak
 FLOPS_EF = 13                # energy+forces: 2 sub, 3 r^2, 1 rsqrt, 1 add, 2 r^-3, 4 FMA
 FLOPS_HVP = 24
+FLOPS_RIESZ = 15             # Riesz-s: 2 sub, 3 r^2, log2, mul, exp2, 2 energy fma, 1 mul, 4 FMA
 
 
 def hip_runtime():
@@ -479,6 +481,12 @@ def main():
                            "alg_tflops": FLOPS_HVP * pairs / (k * 1e-3) / 1e12}
         s, k = timed(lambda: ops.energy(xt, yt, MIXED), 5, 1, lib, hip)
         extra["mixed_energy"] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k}
+        # Riesz-s (1/r^s pairs): the pair term needs log2 and exp2 instead of one rsqrt
+        for name, prec, sv, reps in (("riesz_s2_mixed", MIXED, 2.0, 5), ("riesz_s3_mixed", MIXED, 3.0, 5),
+                                     ("riesz_s2_fp64", FP64, 2.0, 2)):
+            s, k = timed(lambda: ops.riesz(xt, yt, sv, prec), reps, 1, lib, hip)
+            extra[name] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k,
+                           "alg_tflops": FLOPS_RIESZ * pairs / (k * 1e-3) / 1e12}
         out["extra"] = extra
     if not args.no_relax:
         out["relax"] = relax_comparison(xt, yt, args.relax_subset)
