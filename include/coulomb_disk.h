@@ -59,7 +59,8 @@ enum {
   CD_OP_RELAX = 5,
   CD_OP_LANCZOS = 6,
   CD_OP_DEFECT = 7,
-  CD_OP_ZONES = 8
+  CD_OP_ZONES = 8,
+  CD_OP_VORONOI = 9
 };
 
 /* Per-charge flags written by coulomb_validate. */
@@ -286,6 +287,26 @@ int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_
  * synchronise. */
 int border_project(double* x, double* y, int64_t n, const int32_t* flags, double sigma,
                    void* stream);
+
+/* Structure analysis (Sec. III): Voronoi coordination and psi_6.
+ * z[n] (device int32): the number of Voronoi (Delaunay) neighbours of each
+ * charge; -2 for a charge on the convex hull (unbounded cell); -1 only if a
+ * cell needs more than 48 vertices.  Each cell is certified exact: clipped
+ * by every charge in a widening grid neighbourhood until 2|v| <= the
+ * neighbourhood's margin for all its vertices v (relative to the charge).
+ * psi6 (nullable, device double [2n]): real and imaginary part of
+ * psi_6(i) = (1/z_i) sum_j ((r_j - r_i)/|r_j - r_i|)^6 over the neighbours
+ * (0 for z <= 0).  Charges must be distinct and inside |r| <= 1 + 1e-9.
+ * ws: coulomb_workspace_bytes(CD_OP_VORONOI, n, 0, 0, 0) bytes.  Does not
+ * synchronise. */
+int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z, double* psi6,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Radial counts: counts[nbins] (device int32) of |r| = sqrt((x*x) + (y*y))
+ * (each operation rounded once) in the bins floor(|r| nbins), the last bin
+ * also taking |r| >= 1.  Does not synchronise. */
+int radial_histogram(const double* x, const double* y, int64_t n, int32_t nbins, int32_t* counts,
+                     void* stream);
 
 /* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
  * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE

@@ -10,6 +10,8 @@ imports the GPU library.
   Delaunay neighbours, from scipy's Delaunay triangulation (a library
   primitive, as a sort or a matmul would be).
 * ``coordination``       -- z_i, the number of Voronoi neighbours.
+* ``voronoi_z``          -- the same with -2 for charges on the convex hull
+  (scipy's ConvexHull), whose Voronoi cells are unbounded.
 * ``psi6``               -- psi_6(i) = (1/z_i) sum over the neighbours j of
   exp(6 i theta_ij), theta_ij the angle of r_j - r_i.
 * ``radial_counts``      -- counts of |r| in nbins equal bins of [0, 1]
@@ -37,6 +39,20 @@ def voronoi_neighbours(x, y):
 
 def coordination(x, y):
     return np.array([v.size for v in voronoi_neighbours(x, y)], dtype=np.int32)
+
+
+def hull_points(x, y):
+    from scipy.spatial import ConvexHull
+    pts = np.stack([np.asarray(x, np.float64), np.asarray(y, np.float64)], 1)
+    m = np.zeros(pts.shape[0], dtype=bool)
+    m[ConvexHull(pts).vertices] = True
+    return m
+
+
+def voronoi_z(x, y):
+    z = coordination(x, y)
+    z[hull_points(x, y)] = -2
+    return z
 
 
 def psi6(x, y, neighbours=None):

@@ -1218,6 +1218,7 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
                              int precision);
 size_t lanczos_workspace_bytes(int64_t n, int k);
 size_t zones_workspace_bytes(int op, int64_t n, int32_t n_zones);
+size_t structure_workspace_bytes(int64_t n);
 
 }  // namespace cd
 
@@ -1241,6 +1242,10 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
     return most;
   }
   if (op == CD_OP_LANCZOS) return cd::lanczos_workspace_bytes(n, n_patches);
+  if (op == CD_OP_VORONOI) {
+    if (n < 1 || n > (1 << 26)) return 0;
+    return cd::structure_workspace_bytes(n);
+  }
   if (op == CD_OP_DEFECT || op == CD_OP_ZONES) {
     if (n < 1 || n > (1 << 26) || (op == CD_OP_ZONES && n_patches < 1)) return 0;
     return cd::zones_workspace_bytes(op, n, n_patches);

@@ -1,0 +1,355 @@
+// Structure analysis of a configuration (paper Sec. III: Voronoi
+// coordination, the bond-orientational order psi_6, the radial density).
+//
+// Voronoi cells.  The charges are binned on a uniform grid of cells about
+// one mean spacing wide (counting sort; each cell's list is then put in
+// index order, so everything downstream is deterministic).  One thread per
+// charge i clips a large square around r_i by the bisector half-plane of
+// every charge j in the (2R+1)^2 cells around its own (Sutherland-Hodgman in
+// coordinates relative to r_i, FP64); each polygon edge remembers the charge
+// whose bisector made it.  A charge j outside the searched block lies
+// farther than its distance D from r_i (D: the block's margin around r_i,
+// unbounded where the block reaches the grid's edge); it can cut a vertex v
+// only if |r_j - r_i| < 2|v|.  So a bounded cell is final when every vertex
+// satisfies 2|v| <= D; otherwise the search widens (k_voronoi).  Charges on
+// the convex hull have unbounded cells and report z = -2.
+// z_i = number of bisector edges = Voronoi (Delaunay) neighbours;
+// psi_6(i) = (1/z_i) sum_j u_ij^6, u_ij = (r_j - r_i)/|r_j - r_i| as a complex
+// number.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace cd {
+
+constexpr int kVorR = 2;       // cells searched on each side of the charge's cell
+constexpr int kVorMaxV = 48;   // polygon vertices
+constexpr double kVorBox = 4.0;
+constexpr double kGridL = 1.0 + 1e-9;  // the grid covers [-L, L]^2
+constexpr int kScanT = 1024;
+
+struct Grid {
+  int G;       // cells per side
+  double c;    // cell width
+};
+
+__host__ __device__ inline Grid make_grid(int64_t n) {
+  const double h = sqrt(2.0 * 3.141592653589793 / (sqrt(3.0) * (double)n));
+  double g = floor(2.0 * kGridL / h);
+  if (g < 1.0) g = 1.0;
+  if (g > 4096.0) g = 4096.0;
+  Grid q;
+  q.G = (int)g;
+  q.c = 2.0 * kGridL / q.G;
+  return q;
+}
+
+size_t structure_workspace_bytes(int64_t n) {
+  const Grid g = make_grid(n);
+  const size_t cells = (size_t)g.G * g.G;
+  Carve cv;
+  cv.take<int32_t>(cells + 1);  // counts, then starts
+  cv.take<int32_t>(cells);      // fill cursors
+  cv.take<int32_t>((size_t)n);  // cell of each charge
+  cv.take<int32_t>((size_t)n);  // charges by cell
+  return cv.off + 256;
+}
+
+__device__ __forceinline__ int cell_coord(double v, const Grid& g) {
+  int k = (int)floor((v + kGridL) / g.c);
+  return k < 0 ? 0 : (k >= g.G ? g.G - 1 : k);
+}
+
+__global__ void k_fill_int(int32_t* __restrict__ a, int m, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) a[i] = v;
+}
+
+__global__ void k_cell_count(const double* __restrict__ x, const double* __restrict__ y, int n,
+                             Grid g, int32_t* __restrict__ count, int32_t* __restrict__ cell) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_coord(y[i], g) * g.G + cell_coord(x[i], g);
+  cell[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan of m counts in place (one workgroup, chunks of kScanT with a
+// running carry); a[m] receives the total.
+__global__ __launch_bounds__(kScanT) void k_cell_scan(int32_t* __restrict__ a, int m) {
+  __shared__ int32_t ws[kScanT / 64];
+  int carry = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < m; c0 += kScanT) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < m ? a[i] : 0;
+    int s = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(s, off, 64);
+      if (lane >= off) s += u;
+    }
+    if (lane == 63) ws[w] = s;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < kScanT / 64; ++q) {
+      before += q < w ? ws[q] : 0;
+      total += ws[q];
+    }
+    __syncthreads();
+    if (i < m) a[i] = carry + before + s - v;
+    carry += total;
+  }
+  if (threadIdx.x == 0) a[m] = carry;
+}
+
+__global__ void k_cell_fill(int n, const int32_t* __restrict__ cell,
+                            const int32_t* __restrict__ start, int32_t* __restrict__ cursor,
+                            int32_t* __restrict__ slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell[i];
+  slot[start[c] + atomicAdd(&cursor[c], 1)] = i;
+}
+
+// Each cell's charges in increasing index order (insertion sort; cells hold
+// a handful of charges).
+__global__ void k_cell_sort(int m, const int32_t* __restrict__ start, int32_t* __restrict__ slot) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int a = start[c], b = start[c + 1];
+  for (int k = a + 1; k < b; ++k) {
+    const int v = slot[k];
+    int q = k - 1;
+    while (q >= a && slot[q] > v) {
+      slot[q + 1] = slot[q];
+      --q;
+    }
+    slot[q + 1] = v;
+  }
+}
+
+// Clip the square of half-width B around r_i by the bisectors of the charges
+// in cells [x0, x1] x [y0, y1], taken ring by ring around the home cell
+// (cx, cy) so that near charges cut first; a charge of ring k >= 1 lies at
+// least (k - 1) c from r_i and can cut only vertices farther than half that,
+// so the rings stop once (k - 1) c >= 2 max|v|.  Returns the vertex count
+// (kVorMaxV + 1 on overflow) with the polygon in buffer `cur`.
+__device__ __forceinline__ bool clip_one(double dx, double dy, int j, int& nv, int& cur,
+                                         double (&px)[2][kVorMaxV], double (&py)[2][kVorMaxV],
+                                         int (&lab)[2][kVorMaxV]) {
+  const double hd = 0.5 * (dx * dx + dy * dy);
+  if (!(hd > 0.0)) return true;  // a coincident charge has no bisector
+  // f(v) = v.d - |d|^2/2 <= 0 keeps v
+  bool any_out = false;
+  for (int q = 0; q < nv; ++q) any_out |= px[cur][q] * dx + py[cur][q] * dy - hd > 0.0;
+  if (!any_out) return true;
+  const int nx = cur ^ 1;
+  int m = 0;
+  for (int q = 0; q < nv; ++q) {
+    const int r = q + 1 == nv ? 0 : q + 1;
+    const double ax = px[cur][q], ay = py[cur][q], bx = px[cur][r], by = py[cur][r];
+    const double fa = ax * dx + ay * dy - hd, fb = bx * dx + by * dy - hd;
+    if (fa <= 0.0) {
+      if (m < kVorMaxV) {
+        px[nx][m] = ax;
+        py[nx][m] = ay;
+        lab[nx][m] = lab[cur][q];
+      }
+      ++m;
+      if (fb > 0.0) {
+        const double t = fa / (fa - fb);
+        if (m < kVorMaxV) {
+          px[nx][m] = ax + t * (bx - ax);
+          py[nx][m] = ay + t * (by - ay);
+          lab[nx][m] = j;
+        }
+        ++m;
+      }
+    } else if (fb <= 0.0) {
+      const double t = fa / (fa - fb);
+      if (m < kVorMaxV) {
+        px[nx][m] = ax + t * (bx - ax);
+        py[nx][m] = ay + t * (by - ay);
+        lab[nx][m] = lab[cur][q];
+      }
+      ++m;
+    }
+  }
+  cur = nx;
+  if (m > kVorMaxV) return false;
+  nv = m;
+  return true;
+}
+
+__device__ int clip_cell(const double* __restrict__ x, const double* __restrict__ y, int i,
+                         double xi, double yi, const Grid& g, const int32_t* __restrict__ start,
+                         const int32_t* __restrict__ slot, int cx, int cy, int x0, int x1,
+                         int y0, int y1, double B, double (&px)[2][kVorMaxV],
+                         double (&py)[2][kVorMaxV], int (&lab)[2][kVorMaxV], int& cur) {
+  cur = 0;
+  int nv = 4;
+  px[0][0] = -B; py[0][0] = -B; lab[0][0] = -1;
+  px[0][1] = B;  py[0][1] = -B; lab[0][1] = -1;
+  px[0][2] = B;  py[0][2] = B;  lab[0][2] = -1;
+  px[0][3] = -B; py[0][3] = B;  lab[0][3] = -1;
+  const int kmax = max(max(cx - x0, x1 - cx), max(cy - y0, y1 - cy));
+  for (int k = 0; k <= kmax; ++k) {
+    if (k >= 2) {
+      double rho = 0.0;
+      for (int q = 0; q < nv; ++q)
+        rho = fmax(rho, sqrt(px[cur][q] * px[cur][q] + py[cur][q] * py[cur][q]));
+      if ((k - 1) * g.c >= 2.0 * rho) break;
+    }
+    for (int qy = max(y0, cy - k); qy <= min(y1, cy + k); ++qy) {
+      const bool edge_row = qy == cy - k || qy == cy + k;
+      for (int qx = max(x0, cx - k); qx <= min(x1, cx + k); ++qx) {
+        if (!edge_row && qx != cx - k && qx != cx + k) continue;  // ring k only
+        const int c = qy * g.G + qx;
+        for (int t = start[c]; t < start[c + 1]; ++t) {
+          const int j = slot[t];
+          if (j == i) continue;
+          if (!clip_one(x[j] - xi, y[j] - yi, j, nv, cur, px, py, lab)) return kVorMaxV + 1;
+        }
+      }
+    }
+  }
+  return nv;
+}
+
+// The search widens (2, 6, 18, .. cells on each side, then the whole grid)
+// until the cell is certified: bounded (no edge on the square) with
+// 2 max|v| <= the block's margin.  With the whole grid searched every charge
+// has clipped, so the cell is exact; if it still reaches the square, the
+// square grows to 1e4 (a bounded cell of a charge next to the boundary can
+// have far vertices), and a cell that reaches even that one is unbounded: the
+// charge lies on the convex hull (z = -2, psi_6 = 0).
+__global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
+                                                const double* __restrict__ y, int n, Grid g,
+                                                const int32_t* __restrict__ start,
+                                                const int32_t* __restrict__ slot,
+                                                int32_t* __restrict__ zout,
+                                                double* __restrict__ psi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  double px[2][kVorMaxV], py[2][kVorMaxV];
+  int lab[2][kVorMaxV];
+  const int cx = cell_coord(xi, g), cy = cell_coord(yi, g);
+  int R = kVorR, cur = 0, nv = 0, z = -1;
+  double B = kVorBox;
+  bool hull = false;
+  for (;;) {
+    const int x0 = max(0, cx - R), x1 = min(g.G - 1, cx + R);
+    const int y0 = max(0, cy - R), y1 = min(g.G - 1, cy + R);
+    nv = clip_cell(x, y, i, xi, yi, g, start, slot, cx, cy, x0, x1, y0, y1, B, px, py, lab, cur);
+    if (nv > kVorMaxV) break;  // z = -1: more vertices than the polygon holds
+    // the searched block's margin around r_i (unbounded where it reaches the grid's edge)
+    const double inf = 1e300;
+    const double ml = x0 == 0 ? inf : xi - (-kGridL + x0 * g.c);
+    const double mr = x1 == g.G - 1 ? inf : (-kGridL + (x1 + 1) * g.c) - xi;
+    const double mb = y0 == 0 ? inf : yi - (-kGridL + y0 * g.c);
+    const double mt = y1 == g.G - 1 ? inf : (-kGridL + (y1 + 1) * g.c) - yi;
+    const double D = fmin(fmin(ml, mr), fmin(mb, mt));
+    bool box = false;
+    double rho = 0.0;
+    for (int q = 0; q < nv; ++q) {
+      box |= lab[cur][q] < 0;
+      rho = fmax(rho, sqrt(px[cur][q] * px[cur][q] + py[cur][q] * py[cur][q]));
+    }
+    const bool full = x0 == 0 && y0 == 0 && x1 == g.G - 1 && y1 == g.G - 1;
+    if (!box && 2.0 * rho <= D) {
+      z = 0;
+      break;
+    }
+    if (full && box && B < 1e4) {
+      B = 1e4;
+      continue;
+    }
+    if (full) {
+      hull = box;
+      z = 0;
+      break;
+    }
+    R *= 3;
+  }
+  double sre = 0.0, sim = 0.0;
+  if (z == 0 && !hull) {
+    for (int q = 0; q < nv; ++q) {
+      const int j = lab[cur][q];
+      if (j < 0) continue;
+      ++z;
+      const double dx = x[j] - xi, dy = y[j] - yi;
+      const double r = sqrt(dx * dx + dy * dy);
+      const double ur = dx / r, ui = dy / r;
+      const double u2r = ur * ur - ui * ui, u2i = 2.0 * ur * ui;
+      const double u4r = u2r * u2r - u2i * u2i, u4i = 2.0 * u2r * u2i;
+      sre += u4r * u2r - u4i * u2i;
+      sim += u4r * u2i + u4i * u2r;
+    }
+  }
+  zout[i] = hull ? -2 : z;
+  if (psi) {
+    psi[2 * (size_t)i] = z > 0 ? sre / z : 0.0;
+    psi[2 * (size_t)i + 1] = z > 0 ? sim / z : 0.0;
+  }
+}
+
+#pragma clang fp contract(off)
+__global__ void k_radial(const double* __restrict__ x, const double* __restrict__ y, int n,
+                         int nbins, int32_t* __restrict__ counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i] * x[i], b = y[i] * y[i];
+  const double r = sqrt(a + b);
+  const double f = floor(r * (double)nbins);
+  int k = f < 0.0 ? 0 : (f >= (double)nbins ? nbins - 1 : (int)f);
+  if (!(r == r)) k = nbins - 1;  // NaN
+  atomicAdd(&counts[k], 1);
+}
+#pragma clang fp contract(on)
+
+}  // namespace cd
+
+using namespace cd;
+
+extern "C" {
+
+int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z, double* psi6,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !y || !z || n < 1 || n > (1 << 26)) return CD_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < structure_workspace_bytes(n)) return CD_ERR_WORKSPACE;
+  const Grid g = make_grid(n);
+  const int cells = g.G * g.G;
+  Carve cv;
+  cv.base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  int32_t* start = cv.take<int32_t>((size_t)cells + 1);
+  int32_t* cursor = cv.take<int32_t>((size_t)cells);
+  int32_t* cell = cv.take<int32_t>((size_t)n);
+  int32_t* slot = cv.take<int32_t>((size_t)n);
+  hipStream_t st = (hipStream_t)stream;
+  const int nn = (int)n;
+  hipLaunchKernelGGL(k_fill_int, dim3((cells + 256) / 256), dim3(256), 0, st, start, cells + 1, 0);
+  hipLaunchKernelGGL(k_fill_int, dim3((cells + 255) / 256), dim3(256), 0, st, cursor, cells, 0);
+  hipLaunchKernelGGL(k_cell_count, dim3((nn + 255) / 256), dim3(256), 0, st, x, y, nn, g, start,
+                     cell);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanT), 0, st, start, cells);
+  hipLaunchKernelGGL(k_cell_fill, dim3((nn + 255) / 256), dim3(256), 0, st, nn, cell, start,
+                     cursor, slot);
+  hipLaunchKernelGGL(k_cell_sort, dim3((cells + 255) / 256), dim3(256), 0, st, cells, start, slot);
+  hipLaunchKernelGGL(k_voronoi, dim3((nn + 63) / 64), dim3(64), 0, st, x, y, nn, g, start, slot,
+                     z, psi6);
+  return hip_status(hipGetLastError());
+}
+
+int radial_histogram(const double* x, const double* y, int64_t n, int32_t nbins, int32_t* counts,
+                     void* stream) {
+  if (!x || !y || !counts || n < 1 || n > (1 << 26) || nbins < 1 || nbins > (1 << 20))
+    return CD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_int, dim3((nbins + 255) / 256), dim3(256), 0, st, counts, nbins, 0);
+  hipLaunchKernelGGL(k_radial, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, (int)n,
+                     nbins, counts);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

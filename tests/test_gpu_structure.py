@@ -1,0 +1,57 @@
+"""Structure analysis on the GPU against the structure oracle (scipy's
+Delaunay triangulation and convex hull): coordination numbers bit-exact,
+hull charges marked, psi_6 to rounding, radial counts bit-exact; at
+N = 1e5 on the benchmark's lattice as well."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import structure as S
+from paper_2609_24722_amd import structure as ST, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _cmp(dev, x, y, label):
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    z, psi = ST.voronoi(xt, yt)
+    z = z.cpu().numpy()
+    zo = S.voronoi_z(x, y)
+    nb = S.voronoi_neighbours(x, y)
+    po = S.psi6(x, y, nb)
+    po[zo < 0] = 0
+    bad = np.nonzero(z != zo)[0]
+    print(f"[{label}] n={x.size} hull={int((zo == -2).sum())} P6={float((zo == 6).mean()):.4f} "
+          f"mismatch={bad.size} {list(zip(bad[:5], z[bad[:5]], zo[bad[:5]]))}", flush=True)
+    assert bad.size == 0
+    assert np.max(np.abs(psi.cpu().numpy() - po)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["lattice2000", "lattice20000", "uniform3000", "ring"])
+def test_voronoi_matches_oracle(dev, case):
+    if case == "lattice2000":
+        x, y = W.warped_lattice(2000, 0.1, 3)
+    elif case == "lattice20000":
+        x, y = W.warped_lattice(20000, 0.02, 4)
+    elif case == "uniform3000":
+        x, y = W.uniform_disk(3000, 5)
+    else:
+        t = 0.3 + 2 * np.pi * np.arange(7) / 7
+        x, y = np.append(np.cos(t), 0.05), np.append(np.sin(t), -0.02)
+    _cmp(dev, x, y, case)
+
+
+def test_voronoi_n100000(dev):
+    x, y = W.workload(3)
+    _cmp(dev, x, y, "lattice1e5")
+
+
+def test_radial_histogram_exact(dev):
+    x, y = W.uniform_disk(20000, 9)
+    r = np.array([0.0, 0.05, 0.1, 0.35, 0.5, 0.999, 1.0, 0.25])
+    x = np.concatenate([x, r])
+    y = np.concatenate([y, np.zeros(r.size)])
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    for nb in (1, 4, 50, 1000):
+        c = ST.radial_histogram(xt, yt, nb).cpu().numpy()
+        assert np.array_equal(c, S.radial_counts(x, y, nb)), nb

@@ -46,3 +46,11 @@ def test_radial_counts_exact():
     r = np.array([0.0, 0.05, 0.1, 0.35, 0.5, 0.999, 1.0, 0.25])
     assert S.radial_counts(r, np.zeros(r.size), 4).tolist() == [3, 2, 1, 2]
     assert S.radial_counts(np.zeros(r.size), -r, 4).tolist() == [3, 2, 1, 2]
+
+
+def test_hull_marking():
+    t = 0.3 + 2 * np.pi * np.arange(8) / 8
+    x = np.append(np.cos(t), 0.1)
+    y = np.append(np.sin(t), 0.0)
+    z = S.voronoi_z(x, y)
+    assert (z[:-1] == -2).all() and z[-1] == 8
