@@ -297,10 +297,22 @@ def defect_cycle_run(dev, n, kappa, precision, T=1000, log=None):
     import torch
     from paper_2609_24722_amd import workloads as W
     from paper_2609_24722_amd.cycle import defect_cycle
+    from paper_2609_24722_amd import structure as ST
     x, y = W.workload(3, n)
     xt = torch.tensor(x, device=dev)
     yt = torch.tensor(y, device=dev)
+    before = ST.summary(xt, yt)
     out = defect_cycle(xt, yt, T=T, kappa=kappa, precision=precision, log=log)
+    after = ST.summary(xt, yt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ST.voronoi(xt, yt)
+    torch.cuda.synchronize()
+    vor_ms = (time.perf_counter() - t0) * 1e3
+    for d in (before, after):
+        d.pop("radial_counts")
+    out["structure"] = {"before": before, "after": after, "voronoi_ms": vor_ms,
+                        "note": "Voronoi coordination fractions over charges with bounded cells (hull excluded)"}
     recs = out.pop("batch_records")
     out["batch_zones_first_last"] = [recs[0]["zones"], recs[-1]["zones"]] if recs else []
     out["workload"] = (f"N={n} warped lattice (sigma 0.02 h, seed 1003); T={T} zones, kappa={kappa}, "

@@ -291,14 +291,15 @@ int border_project(double* x, double* y, int64_t n, const int32_t* flags, double
 /* Structure analysis (Sec. III): Voronoi coordination and psi_6.
  * z[n] (device int32): the number of Voronoi (Delaunay) neighbours of each
  * charge; -2 for a charge on the convex hull (unbounded cell); -1 only if a
- * cell needs more than 48 vertices.  Each cell is certified exact: clipped
+ * cell needs more than 48 vertices or reaches 1e4 from its charge.  Each cell is certified exact: clipped
  * by every charge in a widening grid neighbourhood until 2|v| <= the
  * neighbourhood's margin for all its vertices v (relative to the charge).
  * psi6 (nullable, device double [2n]): real and imaginary part of
  * psi_6(i) = (1/z_i) sum_j ((r_j - r_i)/|r_j - r_i|)^6 over the neighbours
  * (0 for z <= 0).  Charges must be distinct and inside |r| <= 1 + 1e-9.
- * ws: coulomb_workspace_bytes(CD_OP_VORONOI, n, 0, 0, 0) bytes.  Does not
- * synchronise. */
+ * The convex hull is found on the host (monotone chain) from a copy of the
+ * positions, so the call synchronises the stream.  ws:
+ * coulomb_workspace_bytes(CD_OP_VORONOI, n, 0, 0, 0) bytes. */
 int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z, double* psi6,
                          void* ws, size_t ws_bytes, void* stream);
 

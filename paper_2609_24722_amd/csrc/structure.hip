@@ -12,11 +12,14 @@
 // unbounded where the block reaches the grid's edge); it can cut a vertex v
 // only if |r_j - r_i| < 2|v|.  So a bounded cell is final when every vertex
 // satisfies 2|v| <= D; otherwise the search widens (k_voronoi).  Charges on
-// the convex hull have unbounded cells and report z = -2.
+// the convex hull (host code, monotone chain) have unbounded cells and report
+// z = -2.
 // z_i = number of bisector edges = Voronoi (Delaunay) neighbours;
 // psi_6(i) = (1/z_i) sum_j u_ij^6, u_ij = (r_j - r_i)/|r_j - r_i| as a complex
 // number.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.hpp"
 
@@ -52,6 +55,7 @@ size_t structure_workspace_bytes(int64_t n) {
   cv.take<int32_t>(cells);      // fill cursors
   cv.take<int32_t>((size_t)n);  // cell of each charge
   cv.take<int32_t>((size_t)n);  // charges by cell
+  cv.take<int32_t>((size_t)n);  // convex-hull flags
   return cv.off + 256;
 }
 
@@ -216,28 +220,33 @@ __device__ int clip_cell(const double* __restrict__ x, const double* __restrict_
   return nv;
 }
 
-// The search widens (2, 6, 18, .. cells on each side, then the whole grid)
-// until the cell is certified: bounded (no edge on the square) with
-// 2 max|v| <= the block's margin.  With the whole grid searched every charge
-// has clipped, so the cell is exact; if it still reaches the square, the
-// square grows to 1e4 (a bounded cell of a charge next to the boundary can
-// have far vertices), and a cell that reaches even that one is unbounded: the
-// charge lies on the convex hull (z = -2, psi_6 = 0).
+// Charges on the convex hull (found on the host) have unbounded cells:
+// z = -2, psi_6 = 0.  For the others the search widens (2, 6, 18, .. cells
+// on each side, then the whole grid) until the cell is certified: no edge on
+// the square and 2 max|v| <= the block's margin.  With the whole grid
+// searched every charge has clipped; a cell that still reaches the square
+// extends beyond it (a charge next to the boundary can have far vertices), so
+// the square grows to 1e4 once; z = -1 if even that does not hold it.
 __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
                                                 const double* __restrict__ y, int n, Grid g,
                                                 const int32_t* __restrict__ start,
                                                 const int32_t* __restrict__ slot,
+                                                const int32_t* __restrict__ hullf,
                                                 int32_t* __restrict__ zout,
                                                 double* __restrict__ psi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (hullf[i]) {  // on the convex hull: unbounded cell
+    zout[i] = -2;
+    if (psi) psi[2 * (size_t)i] = psi[2 * (size_t)i + 1] = 0.0;
+    return;
+  }
   const double xi = x[i], yi = y[i];
   double px[2][kVorMaxV], py[2][kVorMaxV];
   int lab[2][kVorMaxV];
   const int cx = cell_coord(xi, g), cy = cell_coord(yi, g);
   int R = kVorR, cur = 0, nv = 0, z = -1;
   double B = kVorBox;
-  bool hull = false;
   for (;;) {
     const int x0 = max(0, cx - R), x1 = min(g.G - 1, cx + R);
     const int y0 = max(0, cy - R), y1 = min(g.G - 1, cy + R);
@@ -265,15 +274,11 @@ __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
       B = 1e4;
       continue;
     }
-    if (full) {
-      hull = box;
-      z = 0;
-      break;
-    }
+    if (full) break;  // z = -1
     R *= 3;
   }
   double sre = 0.0, sim = 0.0;
-  if (z == 0 && !hull) {
+  if (z == 0) {
     for (int q = 0; q < nv; ++q) {
       const int j = lab[cur][q];
       if (j < 0) continue;
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
       sim += u4r * u2i + u4i * u2r;
     }
   }
-  zout[i] = hull ? -2 : z;
+  zout[i] = z;
   if (psi) {
     psi[2 * (size_t)i] = z > 0 ? sre / z : 0.0;
     psi[2 * (size_t)i + 1] = z > 0 ? sim / z : 0.0;
@@ -312,6 +317,35 @@ __global__ void k_radial(const double* __restrict__ x, const double* __restrict_
 
 using namespace cd;
 
+namespace {
+
+// Vertices of the convex hull (Andrew's monotone chain; points on an edge
+// between two vertices are not vertices).  flags[i] = 1 for a vertex.
+void hull_flags(const std::vector<double>& x, const std::vector<double>& y,
+                std::vector<int32_t>& flags) {
+  const int n = (int)x.size();
+  std::vector<int> o(n);
+  for (int i = 0; i < n; ++i) o[i] = i;
+  std::sort(o.begin(), o.end(), [&](int a, int b) { return x[a] < x[b] || (x[a] == x[b] && y[a] < y[b]); });
+  auto cross = [&](int a, int b, int c) {
+    return (x[b] - x[a]) * (y[c] - y[a]) - (y[b] - y[a]) * (x[c] - x[a]);
+  };
+  std::vector<int> h(2 * (size_t)n + 2);
+  int k = 0;
+  for (int t = 0; t < n; ++t) {  // lower hull
+    while (k >= 2 && cross(h[k - 2], h[k - 1], o[t]) <= 0.0) --k;
+    h[k++] = o[t];
+  }
+  for (int t = n - 2, lo = k + 1; t >= 0; --t) {  // upper hull
+    while (k >= lo && cross(h[k - 2], h[k - 1], o[t]) <= 0.0) --k;
+    h[k++] = o[t];
+  }
+  flags.assign(n, 0);
+  for (int t = 0; t < k; ++t) flags[h[t]] = 1;
+}
+
+}  // namespace
+
 extern "C" {
 
 int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z, double* psi6,
@@ -326,8 +360,21 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
   int32_t* cursor = cv.take<int32_t>((size_t)cells);
   int32_t* cell = cv.take<int32_t>((size_t)n);
   int32_t* slot = cv.take<int32_t>((size_t)n);
+  int32_t* hullf = cv.take<int32_t>((size_t)n);
   hipStream_t st = (hipStream_t)stream;
   const int nn = (int)n;
+  {
+    std::vector<double> hx(n), hy(n);
+    std::vector<int32_t> hf;
+    int rc = hip_status(hipMemcpyAsync(hx.data(), x, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    if (!rc) rc = hip_status(hipMemcpyAsync(hy.data(), y, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));
+    if (rc) return rc;
+    hull_flags(hx, hy, hf);
+    rc = hip_status(hipMemcpyAsync(hullf, hf.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));  // hf is released on return
+    if (rc) return rc;
+  }
   hipLaunchKernelGGL(k_fill_int, dim3((cells + 256) / 256), dim3(256), 0, st, start, cells + 1, 0);
   hipLaunchKernelGGL(k_fill_int, dim3((cells + 255) / 256), dim3(256), 0, st, cursor, cells, 0);
   hipLaunchKernelGGL(k_cell_count, dim3((nn + 255) / 256), dim3(256), 0, st, x, y, nn, g, start,
@@ -337,7 +384,7 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
                      cursor, slot);
   hipLaunchKernelGGL(k_cell_sort, dim3((cells + 255) / 256), dim3(256), 0, st, cells, start, slot);
   hipLaunchKernelGGL(k_voronoi, dim3((nn + 63) / 64), dim3(64), 0, st, x, y, nn, g, start, slot,
-                     z, psi6);
+                     hullf, z, psi6);
   return hip_status(hipGetLastError());
 }
 
