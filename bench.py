@@ -12,7 +12,8 @@ Printed: one JSON line with the driver's fields plus
                 events recorded around that kernel on its stream);
   cpu_baseline  the CPU oracle on a bounded sample of rows of the same input;
   extra         FP64 energy+forces, HVP (both precisions), energy-only rates and the
-                Riesz-s generalisation (s = 2, 3 mixed; s = 2 FP64).
+                Riesz-s generalisation (s = 2, 3 mixed; s = 2 and 1.7 FP64: powers of
+                1/r when 2s is an integer, pow otherwise).
 
   relax         the batched subdomain relax of 256 patches (sizes U{200..5000})
                 on the same configuration, mixed path, seconds per batch ("cycle");
@@ -495,7 +496,7 @@ def main():
         extra["mixed_energy"] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k}
         # Riesz-s (1/r^s pairs): the pair term needs log2 and exp2 instead of one rsqrt
         for name, prec, sv, reps in (("riesz_s2_mixed", MIXED, 2.0, 5), ("riesz_s3_mixed", MIXED, 3.0, 5),
-                                     ("riesz_s2_fp64", FP64, 2.0, 2)):
+                                     ("riesz_s2_fp64", FP64, 2.0, 2), ("riesz_s1.7_fp64", FP64, 1.7, 2)):
             s, k = timed(lambda: ops.riesz(xt, yt, sv, prec), reps, 1, lib, hip)
             extra[name] = {"pairs_per_s": pairs / (s * 1e-3), "ms": s, "kernel_ms": k,
                            "alg_tflops": FLOPS_RIESZ * pairs / (k * 1e-3) / 1e12}

@@ -91,7 +91,8 @@ int coulomb_forces(const double* x, const double* y, int64_t n, int precision, d
  * s = 1 is the Coulomb case of coulomb_forces.  0 < s <= 6 on CD_MIXED
  * (FP32 pair terms 2^((-s/2-1) log2 r^2) from the hardware log2/exp2, so
  * close pairs must keep r^(-s-2) within FP32 range), 0 < s <= 64 on CD_FP64
- * (pow).  ws: coulomb_workspace_bytes(CD_OP_FORCES, n, 0, 0, precision). */
+ * (powers of the refined FP64 1/r when s is an integer up to 32, of its
+ * square root when 2s is, else pow).  ws: coulomb_workspace_bytes(CD_OP_FORCES, n, 0, 0, precision). */
 int coulomb_riesz(const double* x, const double* y, int64_t n, double s, int precision,
                   double* fx, double* fy, double* e_total, void* ws, size_t ws_bytes,
                   void* stream);

@@ -754,6 +754,8 @@ struct OneArgs {
   const double* vys;
   int n, nb, npad, jb;  // jb = j blocks per split
   double rs;            // kRiesz: the exponent s
+  int rn;               // kRiesz: r^-s = b^rn with b = 1/r (rh = 0) or sqrt(1/r) (rh = 1)
+  int rh;               //   when s (rh = 0) or 2s (rh = 1) is an integer in 1..32; rn = 0: pow
   double* p0;        // [splits][npad]
   double* p1;
   double* p2;
@@ -765,17 +767,32 @@ __device__ __forceinline__ void one64_block(const double* __restrict__ xb,
                                             const double* __restrict__ vxb,
                                             const double* __restrict__ vyb, int jn, double xi,
                                             double yi, double vxi, double vyi, int lane,
-                                            double& A0, double& A1, double& A2, double rs) {
+                                            double& A0, double& A1, double& A2, double rs,
+                                            int rn, int rh) {
 #pragma unroll 4
   for (int jj = 0; jj < jn; ++jj) {
     const double dx = xi - xb[jj], dy = yi - yb[jj];
     const double r2 = __builtin_fma(dx, dx, dy * dy);
     if (MODE == kRiesz) {
-      // r^-s by pow; the self pair is taken at r2 = 1 and zeroed
+      // r^-s: for s an integer the s-th power of 1/r (refined rsqrt, binary
+      // powering), for 2s an integer the 2s-th power of sqrt(1/r); otherwise
+      // pow.  The self pair is taken at r2 = 1 and zeroed.
       const bool self = SELF && jj == lane;
       const double q2 = self ? 1.0 : r2;
-      const double p = self ? 0.0 : pow(q2, -0.5 * rs);
-      const double w = rs * p / q2;
+      double p, w;
+      if (rn > 0) {
+        const double inv = rsqrt64(q2);
+        double b = rh ? sqrt(inv) : inv, acc = 1.0;
+        for (int e = rn; e > 0; e >>= 1) {
+          if (e & 1) acc *= b;
+          b *= b;
+        }
+        p = self ? 0.0 : acc;
+        w = rs * p * (inv * inv);
+      } else {
+        p = self ? 0.0 : pow(q2, -0.5 * rs);
+        w = rs * p / q2;
+      }
       A2 += p;
       A0 = __builtin_fma(dx, w, A0);
       A1 = __builtin_fma(dy, w, A1);
@@ -820,9 +837,11 @@ __global__ __launch_bounds__(256) void k_one64(OneArgs a) {
     const double* vyb = MODE == kHvp ? a.vys + (size_t)J * kBlk : nullptr;
     const int jn = min(kBlk, a.n - J * kBlk);  // real charges only; pads never enter
     if (J == I)
-      one64_block<MODE, true>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs);
+      one64_block<MODE, true>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs,
+                              a.rn, a.rh);
     else
-      one64_block<MODE, false>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs);
+      one64_block<MODE, false>(xb, yb, vxb, vyb, jn, xi, yi, vxi, vyi, lane, A0, A1, A2, a.rs,
+                               a.rn, a.rh);
   }
   const size_t k = (size_t)blockIdx.y * a.npad + si;
   if (MODE == kEnergy) {
@@ -1150,6 +1169,15 @@ static void run_one64(const Plan& P, hipStream_t st, double* out0, double* out1,
                       double riesz_s = 0.0) {
   OneArgs a;
   a.rs = riesz_s;
+  const double r2s = 2.0 * riesz_s;
+  a.rn = 0;
+  a.rh = 0;
+  if (riesz_s == floor(riesz_s) && riesz_s >= 1.0 && riesz_s <= 32.0) {
+    a.rn = (int)riesz_s;
+  } else if (r2s == floor(r2s) && r2s >= 1.0 && r2s <= 32.0) {
+    a.rn = (int)r2s;
+    a.rh = 1;
+  }
   a.xs = P.xs;
   a.ys = P.ys;
   a.vxs = P.vxs;

@@ -66,7 +66,8 @@ def perturb_relax_cycles(x, y, cycles: int, n_patches: int = 64, size_lo: int = 
 def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_defect: float = 0.8,
                  n_lo: int = 200, n_hi: int = 4000, period: int = 250, gap_h: float = 2.0,
                  seed: int = 1006, precision: int = MIXED, gtol: float = 1e-3, log=None, inspect=None,
-                 border_nb: int | None = None, sigma_start: float | None = None, sigma_end: float = 1.0):
+                 border_nb: int | None = None, sigma_start: float | None = None, sigma_end: float = 1.0,
+                 lbfgs_m: int = 16):
     """One defect-targeted cycle of T subdomain optimisations (Sec. II.C).
     x, y: device float64 tensors, updated in place.
 
@@ -140,7 +141,8 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
         sig = 0.0
         if flags is not None:
             sig = s0 + (sigma_end - s0) * (b / max(1, nb - 1))
-        res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol, sigma=sig, boundary=flags)
+        res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol, sigma=sig, boundary=flags,
+                                 lbfgs_m=lbfgs_m)
         com, dc = R.commit_patches(x, y, ptr, idx, res.x, res.y, res.dE.cpu().numpy())
         tracked += float(dc[com == 1].sum())
         st = np.bincount(res.status.cpu().numpy(), minlength=4)[:4]
