@@ -63,6 +63,37 @@ def test_build_patches_bit_exact(dev):
     assert np.array_equal(idx.cpu().numpy(), O.patches(lx, ly, centres, sizes))
 
 
+def test_config4_batch_stratified_oracle_check(dev):
+    """The benchmark's relax batch itself (256 patches of U{200..5000} among
+    N = 1e5, start = snapshot, gtol 1e-3, mixed): every patch converged, and
+    the oracle re-evaluates eight patches spread over the size range (E_sub to
+    1e-13, reduced gradient below gtol, exact energy change, held charges
+    pushed outward)."""
+    x, y = W.workload(4)
+    centres, sizes = W.patch_draws(x.size, 256, 200, 5000, 1104)
+    xt, yt = t(x, dev), t(y, dev)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    print("[case] config-4 batch, mixed", flush=True)
+    res = R.relax_subdomains(xt, yt, ptr, idx, precision=MIXED, gtol=1e-3)
+    torch.cuda.synchronize()
+    st = res.status.cpu().numpy()
+    assert (st == 0).all() and (res.gtan_inf.cpu().numpy() <= 1e-3).all()
+    order = np.argsort(sizes, kind="stable")
+    pick = order[np.linspace(0, sizes.size - 1, 8).round().astype(int)]
+    sub_ptr = np.zeros(9, dtype=np.int32)
+    sub_ptr[1:] = np.cumsum(sizes[pick])
+    idx_np = idx.cpu().numpy()
+    class Sub:  # the picked patches' outputs, packed like a batch of 8
+        pass
+    sub = Sub()
+    sl = [slice(ptr[p], ptr[p + 1]) for p in pick]
+    sub.x = torch.tensor(np.concatenate([res.x.cpu().numpy()[s_] for s_ in sl]))
+    sub.y = torch.tensor(np.concatenate([res.y.cpu().numpy()[s_] for s_ in sl]))
+    for name in ("e_sub", "dE", "gtan_inf", "status"):
+        setattr(sub, name, torch.tensor(getattr(res, name).cpu().numpy()[pick]))
+    check_endpoints(x, y, sub_ptr, np.concatenate([idx_np[s_] for s_ in sl]), sub, 1e-3, "config4")
+
+
 @pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
 def test_relax_small_batch_endpoints(dev, prec):
     x, y = W.warped_lattice(3000, 0.1, 7)
