@@ -1717,9 +1717,12 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   // exact energy and reduced gradient at the final positions, then the exact
   // energy change from the snapshot
   hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
-  exact_grad(1);
-  hipLaunchKernelGGL(k_finish, dim3(n_patches), dim3(kUpd), 0, st, D, o.gtol,
-                     o.precision == CD_FP64 ? 1 : 0, x_out, y_out, e_sub, gtan_inf, iters, status);
+  if (x_out || e_sub || gtan_inf || iters || status) {  // a call for dE alone skips them
+    exact_grad(1);
+    hipLaunchKernelGGL(k_finish, dim3(n_patches), dim3(kUpd), 0, st, D, o.gtol,
+                       o.precision == CD_FP64 ? 1 : 0, x_out, y_out, e_sub, gtan_inf, iters,
+                       status);
+  }
   if (dE) {
     hipLaunchKernelGGL(k_exact<kDelta>, eg, eb, 0, st, D);
     hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, D, (int)kDelta);
