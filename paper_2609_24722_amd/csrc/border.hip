@@ -119,9 +119,10 @@ using namespace cd;
 
 extern "C" {
 
+#pragma clang fp contract(off)
 int32_t border_count(int64_t n) {
   if (n < 1) return 0;
-  const double c = cbrt((double)n);
+  const double c = pow((double)n, 1.0 / 3.0);
   const double v = floor(2.84328 * c * c - 0.530196 * c - 2.32866 + 0.5);
   if (v < 0.0) return 0;
   return v > (double)n ? (int32_t)n : (int32_t)v;
@@ -131,6 +132,7 @@ double border_sigma0(int64_t n) {
   if (n < 1) return 1.0;
   return 1.0 - 1.0 / (2.0 * sqrt((double)n));
 }
+#pragma clang fp contract(on)
 
 int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_t* flags,
                  void* stream) {
