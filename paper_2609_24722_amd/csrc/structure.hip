@@ -185,10 +185,55 @@ __device__ __forceinline__ bool clip_one(double dx, double dy, int j, int& nv, i
   return true;
 }
 
+// Farthest distance from r_i of a point that could cut vertex v (relative to
+// r_i): such a charge lies in the disk about V = r_i + v through r_i (radius
+// |v|) and in the disk of radius Rb about the origin that holds every
+// charge.  The farthest point of that lens from r_i is the point of circle V
+// opposite r_i, the point of circle Rb opposite r_i, or one of the two circle
+// intersections (each candidate counted when it lies in the other disk; the
+// tests allow slack, which can only add candidates).  Without the Rb disk the
+// bound is 2|v|; with it, the long cells of charges next to the hull, whose
+// far vertices lie well outside the disk, certify at a short range.
+__device__ double lens_reach(double cx, double cy, double vx, double vy, double Rb) {
+  const double rho2 = vx * vx + vy * vy, rho = sqrt(rho2);
+  const double Vx = cx + vx, Vy = cy + vy;
+  const double Ax = Vx + vx, Ay = Vy + vy;
+  const double Rb2 = Rb * Rb;
+  if (Ax * Ax + Ay * Ay <= Rb2 * (1.0 + 1e-9)) return 2.0 * rho;
+  double M = 0.0;
+  const double cn = sqrt(cx * cx + cy * cy);
+  if (cn > 0.0) {
+    const double ex = -Rb * cx / cn - Vx, ey = -Rb * cy / cn - Vy;
+    if (ex * ex + ey * ey <= rho2 * (1.0 + 1e-9)) M = Rb + cn;
+  } else {
+    M = Rb;
+  }
+  const double d2 = Vx * Vx + Vy * Vy, d = sqrt(d2);
+  if (d > 0.0) {
+    const double a = (Rb2 - rho2 + d2) / (2.0 * d);
+    const double hh = Rb2 - a * a;
+    if (hh > -1e-9 * Rb2) {
+      const double h = sqrt(fmax(hh, 0.0));
+      const double ux = Vx / d, uy = Vy / d;
+      const double p1x = a * ux - h * uy - cx, p1y = a * uy + h * ux - cy;
+      const double p2x = a * ux + h * uy - cx, p2y = a * uy - h * ux - cy;
+      M = fmax(M, fmax(sqrt(p1x * p1x + p1y * p1y), sqrt(p2x * p2x + p2y * p2y)));
+    }
+  }
+  return M;
+}
+// lens_reach with slack for rounding, over the polygon's vertices
+__device__ double poly_reach(double xi, double yi, const double* px, const double* py, int nv,
+                             double Rb) {
+  double M = 0.0;
+  for (int q = 0; q < nv; ++q) M = fmax(M, lens_reach(xi, yi, px[q], py[q], Rb));
+  return M * (1.0 + 1e-9) + 1e-12;
+}
+
 __device__ int clip_cell(const double* __restrict__ x, const double* __restrict__ y, int i,
                          double xi, double yi, const Grid& g, const int32_t* __restrict__ start,
                          const int32_t* __restrict__ slot, int cx, int cy, int x0, int x1,
-                         int y0, int y1, double B, double (&px)[2][kVorMaxV],
+                         int y0, int y1, double B, double Rb, double (&px)[2][kVorMaxV],
                          double (&py)[2][kVorMaxV], int (&lab)[2][kVorMaxV], int& cur) {
   cur = 0;
   int nv = 4;
@@ -198,12 +243,7 @@ __device__ int clip_cell(const double* __restrict__ x, const double* __restrict_
   px[0][3] = -B; py[0][3] = B;  lab[0][3] = -1;
   const int kmax = max(max(cx - x0, x1 - cx), max(cy - y0, y1 - cy));
   for (int k = 0; k <= kmax; ++k) {
-    if (k >= 2) {
-      double rho = 0.0;
-      for (int q = 0; q < nv; ++q)
-        rho = fmax(rho, sqrt(px[cur][q] * px[cur][q] + py[cur][q] * py[cur][q]));
-      if ((k - 1) * g.c >= 2.0 * rho) break;
-    }
+    if (k >= 2 && (k - 1) * g.c >= poly_reach(xi, yi, px[cur], py[cur], nv, Rb)) break;
     for (int qy = max(y0, cy - k); qy <= min(y1, cy + k); ++qy) {
       const bool edge_row = qy == cy - k || qy == cy + k;
       for (int qx = max(x0, cx - k); qx <= min(x1, cx + k); ++qx) {
@@ -222,17 +262,18 @@ __device__ int clip_cell(const double* __restrict__ x, const double* __restrict_
 
 // Charges on the convex hull (found on the host) have unbounded cells:
 // z = -2, psi_6 = 0.  For the others the search widens (2, 6, 18, .. cells
-// on each side, then the whole grid) until the cell is certified: no edge on
-// the square and 2 max|v| <= the block's margin.  With the whole grid
-// searched every charge has clipped; a cell that still reaches the square
-// extends beyond it (a charge next to the boundary can have far vertices), so
-// the square grows to 1e4 once; z = -1 if even that does not hold it.
+// on each side, then the whole grid) until every vertex's reach (lens_reach)
+// is within the block's margin: no charge outside can cut the polygon.  A
+// certified polygon with an edge on the square belongs to a cell that
+// extends beyond it (a charge next to the hull can have far vertices): the
+// square grows to 1e4 once, at the same range; z = -1 if even that does not
+// hold it, or if the polygon outgrows its vertex arrays.
 __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
                                                 const double* __restrict__ y, int n, Grid g,
                                                 const int32_t* __restrict__ start,
                                                 const int32_t* __restrict__ slot,
                                                 const int32_t* __restrict__ hullf,
-                                                int32_t* __restrict__ zout,
+                                                double Rb, int32_t* __restrict__ zout,
                                                 double* __restrict__ psi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -250,7 +291,8 @@ __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
   for (;;) {
     const int x0 = max(0, cx - R), x1 = min(g.G - 1, cx + R);
     const int y0 = max(0, cy - R), y1 = min(g.G - 1, cy + R);
-    nv = clip_cell(x, y, i, xi, yi, g, start, slot, cx, cy, x0, x1, y0, y1, B, px, py, lab, cur);
+    nv = clip_cell(x, y, i, xi, yi, g, start, slot, cx, cy, x0, x1, y0, y1, B, Rb, px, py, lab,
+                   cur);
     if (nv > kVorMaxV) break;  // z = -1: more vertices than the polygon holds
     // the searched block's margin around r_i (unbounded where it reaches the grid's edge)
     const double inf = 1e300;
@@ -260,21 +302,19 @@ __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
     const double mt = y1 == g.G - 1 ? inf : (-kGridL + (y1 + 1) * g.c) - yi;
     const double D = fmin(fmin(ml, mr), fmin(mb, mt));
     bool box = false;
-    double rho = 0.0;
-    for (int q = 0; q < nv; ++q) {
-      box |= lab[cur][q] < 0;
-      rho = fmax(rho, sqrt(px[cur][q] * px[cur][q] + py[cur][q] * py[cur][q]));
-    }
+    for (int q = 0; q < nv; ++q) box |= lab[cur][q] < 0;
     const bool full = x0 == 0 && y0 == 0 && x1 == g.G - 1 && y1 == g.G - 1;
-    if (!box && 2.0 * rho <= D) {
-      z = 0;
-      break;
+    if (full || poly_reach(xi, yi, px[cur], py[cur], nv, Rb) <= D) {
+      if (!box) {
+        z = 0;
+        break;
+      }
+      if (B < 1e4) {
+        B = 1e4;
+        continue;
+      }
+      break;  // z = -1
     }
-    if (full && box && B < 1e4) {
-      B = 1e4;
-      continue;
-    }
-    if (full) break;  // z = -1
     R *= 3;
   }
   double sre = 0.0, sim = 0.0;
@@ -363,6 +403,7 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
   int32_t* hullf = cv.take<int32_t>((size_t)n);
   hipStream_t st = (hipStream_t)stream;
   const int nn = (int)n;
+  double Rb = 0.0;  // radius of a disk about the origin that holds every charge
   {
     std::vector<double> hx(n), hy(n);
     std::vector<int32_t> hf;
@@ -371,6 +412,8 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
     if (!rc) rc = hip_status(hipStreamSynchronize(st));
     if (rc) return rc;
     hull_flags(hx, hy, hf);
+    for (int64_t i = 0; i < n; ++i) Rb = fmax(Rb, sqrt(hx[i] * hx[i] + hy[i] * hy[i]));
+    Rb = Rb * (1.0 + 1e-12) + 1e-300;
     rc = hip_status(hipMemcpyAsync(hullf, hf.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     if (!rc) rc = hip_status(hipStreamSynchronize(st));  // hf is released on return
     if (rc) return rc;
@@ -384,7 +427,7 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
                      cursor, slot);
   hipLaunchKernelGGL(k_cell_sort, dim3((cells + 255) / 256), dim3(256), 0, st, cells, start, slot);
   hipLaunchKernelGGL(k_voronoi, dim3((nn + 63) / 64), dim3(64), 0, st, x, y, nn, g, start, slot,
-                     hullf, z, psi6);
+                     hullf, Rb, z, psi6);
   return hip_status(hipGetLastError());
 }
 

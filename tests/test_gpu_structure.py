@@ -13,21 +13,26 @@ pytestmark = pytest.mark.gpu
 
 
 def _cmp(dev, x, y, label):
+    import time
     xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     z, psi = ST.voronoi(xt, yt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
     z = z.cpu().numpy()
     zo = S.voronoi_z(x, y)
     nb = S.voronoi_neighbours(x, y)
     po = S.psi6(x, y, nb)
     po[zo < 0] = 0
     bad = np.nonzero(z != zo)[0]
-    print(f"[{label}] n={x.size} hull={int((zo == -2).sum())} P6={float((zo == 6).mean()):.4f} "
+    print(f"[{label}] n={x.size} {ms:.1f} ms hull={int((zo == -2).sum())} P6={float((zo == 6).mean()):.4f} "
           f"mismatch={bad.size} {list(zip(bad[:5], z[bad[:5]], zo[bad[:5]]))}", flush=True)
     assert bad.size == 0
     assert np.max(np.abs(psi.cpu().numpy() - po)) < 1e-12
 
 
-@pytest.mark.parametrize("case", ["lattice2000", "lattice20000", "uniform3000", "ring"])
+@pytest.mark.parametrize("case", ["lattice2000", "lattice20000", "uniform3000", "ring", "wall_ring"])
 def test_voronoi_matches_oracle(dev, case):
     if case == "lattice2000":
         x, y = W.warped_lattice(2000, 0.1, 3)
@@ -35,6 +40,12 @@ def test_voronoi_matches_oracle(dev, case):
         x, y = W.warped_lattice(20000, 0.02, 4)
     elif case == "uniform3000":
         x, y = W.uniform_disk(3000, 5)
+    elif case == "wall_ring":
+        # a relaxed configuration's outer layer: charges on the unit circle
+        # (all hull vertices) around a denser interior
+        t = 2 * np.pi * (np.arange(800) + np.random.default_rng(6).uniform(-0.2, 0.2, 800)) / 800
+        xi, yi = W.warped_lattice(8000, 0.02, 6)
+        x, y = np.concatenate([np.cos(t), 0.995 * xi]), np.concatenate([np.sin(t), 0.995 * yi])
     else:
         t = 0.3 + 2 * np.pi * np.arange(7) / 7
         x, y = np.append(np.cos(t), 0.05), np.append(np.sin(t), -0.02)
