@@ -596,15 +596,17 @@ __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
   }
 }
 
-// One workgroup per 64-active block; its kMW waves split the patch's j list
+// One workgroup per 64-active block; its MW waves split the patch's j list
 // (actives, then halo) into ranges cut at multiples of 64 and the partial
 // sums are combined in LDS in wave order, so a large patch spreads over
-// kMW times more waves when few patches are still running.
+// MW times more waves.  MW = kMW, or kMWWide when few blocks belong to
+// patches still running (the chip would otherwise sit mostly idle).
 constexpr int kMW = 8;
+constexpr int kMWWide = 16;
 
-template <bool WK>
-__global__ __launch_bounds__(64 * kMW) void k_model(RelaxDev R) {
-  __shared__ double part[kMW][7][64];  // G0 G1 E Ec K0 K1 K2 per wave and lane
+template <bool WK, int MW>
+__global__ __launch_bounds__(64 * MW) void k_model(RelaxDev R) {
+  __shared__ double part[MW][7][64];  // G0 G1 E Ec K0 K1 K2 per wave and lane
   const int wb = blockIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(64 * kMW) void k_model(RelaxDev R) {
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
   const int na = a1 - a0, nj = na + (h1 - h0);
-  const int per = ((nj + kMW - 1) / kMW + 63) & ~63;
+  const int per = ((nj + MW - 1) / MW + 63) & ~63;
   const int j0 = min(nj, w * per), j1 = min(nj, j0 + per);
   const int a = bk.y + lane;
   const bool ok = a < a1;
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(64 * kMW) void k_model(RelaxDev R) {
   if (w != 0 || !ok) return;
   G0 = G1 = E = Ec = 0.0;
   K[0] = K[1] = K[2] = 0.0;
-  for (int q = 0; q < kMW; ++q) {
+  for (int q = 0; q < MW; ++q) {
     G0 += part[q][0][lane];
     G1 += part[q][1][lane];
     const double v = part[q][2][lane], tt = E + v;  // Neumaier across the waves' sums
@@ -984,6 +986,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         if (t == 0) rho[k] = 1.0 / sy;
         s.head = (s.head + 1) % m;
         if (s.mem < m) s.mem++;
+      } else if (s.mem == m) {
+        s.mem = m - 1;  // slot k held the oldest pair, now overwritten by the rejected one
       }
     }
     // move to the trial, update the held set
@@ -1359,6 +1363,7 @@ __global__ __launch_bounds__(kUpd) void k_finish_delta(RelaxDev R, double* __res
 // ------------------------------------------------------------------ planning --
 struct RPlan {
   int n, P, nbN, m, ntot, nblk, splits, jb, hcap;
+  int running;  // patches running at the last read-back (host copy)
   size_t total;
   RelaxDev D;
   int32_t* hcount;  // [P]
@@ -1380,6 +1385,7 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   R.jb = (R.nbN + sp - 1) / sp;
   R.splits = (R.nbN + R.jb - 1) / R.jb;
   R.hcap = precision == CD_MIXED ? 6 * R.ntot + 4096 * P : 0;
+  R.running = P;
   Carve cv;
   cv.base = base;
   RelaxDev& D = R.D;
@@ -1497,6 +1503,7 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Eva
           hipSuccess)
         return CD_ERR_HIP;
       if (hipStreamSynchronize(st) != hipSuccess) return CD_ERR_HIP;
+      R.running = h_running;
       if (h_running <= 0) break;
       if (g_trace && (r & 255) == 255) fprintf(stderr, "[relax] lock-step round %d: %d running\n", r + 1, h_running);
     }
@@ -1663,10 +1670,16 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
       // the Hessian blocks (preconditioner) are evaluated at the expansion
       // point only and kept for the rest of the round
-      if (all)
-        hipLaunchKernelGGL(k_model<true>, dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+      // blocks of running patches, estimated from the running count
+      const bool wide = (int64_t)R.running * D.nblk < (int64_t)512 * n_patches;
+      if (all && wide)
+        hipLaunchKernelGGL((k_model<true, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, st, E);
+      else if (all)
+        hipLaunchKernelGGL((k_model<true, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+      else if (wide)
+        hipLaunchKernelGGL((k_model<false, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, st, E);
       else
-        hipLaunchKernelGGL(k_model<false>, dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+        hipLaunchKernelGGL((k_model<false, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, st, E);
     };
     // rounds: expand the far field exactly at z (one O(n_act N) FP64 pass);
     // the model gradient at its expansion point is the exact gradient, which
@@ -1690,6 +1703,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                                           st))))
         return rc;
       if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+      R.running = hr;
       if (trace) {
         std::vector<PState> hs(n_patches);
         (void)hipMemcpy(hs.data(), D.st, sizeof(PState) * n_patches, hipMemcpyDeviceToHost);

@@ -174,7 +174,7 @@ def test_defect_cycle_border_interior_small(dev):
     xs, ys = xt.cpu().numpy(), yt.cpu().numpy()
     r = np.hypot(xs, ys)
     print(f"[bi-cycle] nb={nb} batches={out['batches']} committed={out['committed']} "
-          f"E {out['E_start']:.10e} -> {out['E_end']:.10e}", flush=True)
+          f"E {out['E_start']:.10e} -> {out['E_end']:.10e} relax_status={out['relax_status']}", flush=True)
     assert out["E_end"] < out["E_start"]
     assert abs(out["tracked_energy"] - out["E_end"]) <= 1e-12 * out["E_end"]
     assert abs(out["E_end"] - O.energy(xs, ys)) <= 1e-13 * out["E_end"]
