@@ -190,7 +190,7 @@ struct RelaxDev {
   int32_t* hptr;           // [P+1] halo CSR
   int32_t* hidx;           // halo charge indices
   int hcap;
-  float *a32x, *a32y;      // actives relative to their patch centre (FP32), refreshed per round
+  float *a32x, *a32y;      // trial actives relative to their patch centre (FP32)
   float *h32x, *h32y;      // halo relative to the patch centre (FP32)
   double *h64x, *h64y;     // halo positions, packed (FP64)
   PState* st;              // [P]
@@ -785,6 +785,37 @@ __device__ void block_sum_max(double& sm, double& mx, WgRed& R) {
   mx = tm;
 }
 
+// Many sums at once.  rows_sum: each 16-lane row adds every one of the N
+// values by DPP, the row's first lane stores the row sums, then a barrier.
+// rows_total: the total of value q from its kRows row sums, in a fixed order
+// (four interleaved partial sums, then (s0 + s1) + (s2 + s3)).
+constexpr int kRows = kUpd / 16;
+template <int N>
+__device__ __forceinline__ void rows_sum(const double (&v)[N], double* part) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double x = v[q];
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    x += dpp_f64<0x141>(x);
+    x += dpp_f64<0x140>(x);
+    if ((t & 15) == 0) part[q * kRows + (t >> 4)] = x;
+  }
+  __syncthreads();
+}
+__device__ __forceinline__ double rows_total(const double* part, int q) {
+  const double* r = part + q * kRows;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = 0; i < kRows; i += 4) {
+    s0 += r[i];
+    s1 += r[i + 1];
+    s2 += r[i + 2];
+    s3 += r[i + 3];
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
 // reduced gradient component magnitude at position (px, py) with gradient g:
 // a charge on its wall (radius sig: 1 for the hard wall of Eq. 3, the
 // interior radius of the border-interior split) whose gradient points inward
@@ -892,6 +923,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   HT* const Yy = reinterpret_cast<HT*>(R.Yy);
   WG_RED_LDS(red);
   __shared__ double s_alf[kMaxMem];
+  __shared__ double s_rho[kMaxMem];  // rho of the patch: the recursion reads it from LDS
+  __shared__ double s_part[8 * kRows];
   __shared__ int s_flag;
   const int p = blockIdx.x, t = threadIdx.x;
   PState s = R.st[p];
@@ -900,6 +933,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int m = R.m;
   double* rho = R.rho + (size_t)p * m;
+  if (t < m) s_rho[t] = rho[t];  // before the first barrier below
+  const double tol = R.ptol ? R.ptol[p] : R.tol;  // loaded ahead of the barriers
 
   // energy of the trial (fixed-order block sum of per-active terms) and the
   // directional derivatives along the step in optimisation coordinates:
@@ -983,7 +1018,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       block_sum3(syp, ssp, yyp, red);
       const double sy = syp, ss = ssp, yy = yyp;
       if (sy > 1e-12 * sqrt(ss * yy)) {
-        if (t == 0) rho[k] = 1.0 / sy;
+        if (t == 0) rho[k] = s_rho[k] = 1.0 / sy;
         s.head = (s.head + 1) % m;
         if (s.mem < m) s.mem++;
       } else if (s.mem == m) {
@@ -1020,15 +1055,33 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     const double gi = block_max(gm, red);
     __syncthreads();
     if (s_flag && s.mem > 0) {
-      for (int k = 0; k < s.mem; ++k) {
-        const int kk = (s.head - 1 - k + m) % m;
-        double sy = 0.0;
+      // entries were cleared: every rho again, eight pairs per pass over the
+      // actives and one many-value sum (thread j < 8 finishes pair 8h + j)
+      const int M = s.mem;
+      for (int h = 0; 8 * h < M; ++h) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = 0.0;
         for (int a = a0 + t; a < a1; a += kUpd) {
-          const size_t q = (size_t)kk * R.ntot + a;
-          sy += (double)Sx[q] * (double)Yx[q] + (double)Sy[q] * (double)Yy[q];
+          int sk = s.head - 8 * h;
+          if (sk <= 0) sk += m;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            sk = sk == 0 ? m - 1 : sk - 1;
+            if (8 * h + j < M) {
+              const size_t q = (size_t)sk * R.ntot + a;
+              v[j] += (double)Sx[q] * (double)Yx[q] + (double)Sy[q] * (double)Yy[q];
+            }
+          }
         }
-        sy = block_sum(sy, red);
-        if (t == 0) rho[kk] = sy > 0.0 ? 1.0 / sy : 0.0;
+        rows_sum<8>(v, s_part);
+        const int jt = 8 * h + t;
+        if (t < 8 && jt < M) {
+          const double sy = rows_total(s_part, t);
+          const int kk = s.head - 1 - jt < 0 ? s.head - 1 - jt + m : s.head - 1 - jt;
+          rho[kk] = s_rho[kk] = sy > 0.0 ? 1.0 / sy : 0.0;
+        }
+        __syncthreads();  // s_part is written again by the next half
       }
     }
     s.E = Et;
@@ -1038,7 +1091,6 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       s.total_it++;
     }
     s.init = 0;
-    const double tol = R.ptol ? R.ptol[p] : R.tol;
     if (gi <= tol || s.it >= R.max_iter) {
       if (t == 0) {
         s.status = gi <= tol ? kConverged : kIterCap;
@@ -1056,6 +1108,10 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
                   R.sigma);
         R.tx[a] = nx;
         R.ty[a] = ny;
+        if (R.a32x) {  // the model's FP32 coordinates of the trial
+          R.a32x[a] = (float)(nx - s.cx);
+          R.a32y[a] = (float)(ny - s.cy);
+        }
       }
       if (t == 0) R.st[p] = s;
       return;
@@ -1099,7 +1155,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
     auto load_pair = [&](int k, HT* u0, HT* u1, HT* w0, HT* w1) {
       const bool kin = k >= 0 && k < s.mem;  // pairs outside the memory read as zero
-      const size_t base = (size_t)((s.head - 1 - (kin ? k : 0) + m) % m) * R.ntot;
+      const int sk = s.head - 1 - (kin ? k : 0);
+      const size_t base = (size_t)(sk < 0 ? sk + m : sk) * R.ntot;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
         const int a = a0 + t + j * kUpd;
@@ -1112,7 +1169,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     };
     if (kPre) load_pair(0, ux, uy, wx, wy);
     for (int k = 0; k < s.mem; ++k) {
-      const int kk = (s.head - 1 - k + m) % m;
+      const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
       const size_t base = (size_t)kk * R.ntot;
       HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
       if (kPre)
@@ -1124,7 +1181,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
       for (int a = tail0; a < a1; a += kUpd)
         v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
-      const double al = rho[kk] * block_sum(v, red);
+      const double rk = s_rho[kk];  // read ahead of the reduction's barrier
+      const double al = rk * block_sum(v, red);
       if (t == 0) s_alf[kk] = al;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
@@ -1169,7 +1227,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     }
     if (kPre) load_pair(s.mem - 1, ux, uy, wx, wy);
     for (int k = s.mem - 1; k >= 0; --k) {
-      const int kk = (s.head - 1 - k + m) % m;
+      const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
       const size_t base = (size_t)kk * R.ntot;
       HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
       if (kPre)
@@ -1181,7 +1239,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
       for (int a = tail0; a < a1; a += kUpd)
         v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
-      const double be = rho[kk] * block_sum(v, red);
+      const double rk = s_rho[kk];
+      const double be = rk * block_sum(v, red);
       const double coef = s_alf[kk] - be;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
@@ -1247,6 +1306,10 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], 1.0, nx, ny, R.pin[a], R.sigma);
     R.tx[a] = nx;
     R.ty[a] = ny;
+    if (R.a32x) {
+      R.a32x[a] = (float)(nx - s.cx);
+      R.a32y[a] = (float)(ny - s.cy);
+    }
   }
   if (t == 0) R.st[p] = s;
 }
@@ -1667,7 +1730,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     auto model = [&](int all) {
       RelaxDev E = D;
       E.eval_all = all;
-      hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
+      // within the rounds k_update writes the FP32 coordinates of each trial
+      if (all) hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
       // the Hessian blocks (preconditioner) are evaluated at the expansion
       // point only and kept for the rest of the round
       // blocks of running patches, estimated from the running count
