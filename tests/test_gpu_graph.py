@@ -1,0 +1,48 @@
+"""The pair calls under HIP graph capture: energy (with local energies),
+forces and HVP, on both paths, captured once and replayed several times with
+eager work of the same library and synchronisations between the replays;
+every replay must reproduce the eager results bit for bit (the kernels sum in
+a fixed order, so a correct replay has no rounding freedom)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_24722_amd import FP64, MIXED, ops, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _calls(xt, yt, vx, vy, prec):
+    E, e = ops.energy(xt, yt, prec, local=True)
+    fx, fy, Ef = ops.forces(xt, yt, prec)
+    hx, hy = ops.hvp(xt, yt, vx, vy, prec)
+    return [E, e, fx, fy, Ef, hx, hy]
+
+
+@pytest.mark.parametrize("prec", [MIXED, FP64])
+def test_pair_calls_replay_bit_exact(dev, prec):
+    n = 6000 if prec == FP64 else 20000
+    x, y = W.warped_lattice(n, 0.02, 71)
+    rng = np.random.default_rng(72)
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    vx = torch.tensor(rng.standard_normal(n), device=dev)
+    vy = torch.tensor(rng.standard_normal(n), device=dev)
+    want = [t.clone() for t in _calls(xt, yt, vx, vy, prec)]  # eager, also sizes the workspaces
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        got = _calls(xt, yt, vx, vy, prec)
+    torch.cuda.synchronize()
+    x2, y2 = W.warped_lattice(n, 0.05, 73)
+    x2t, y2t = torch.tensor(x2, device=dev), torch.tensor(y2, device=dev)
+    for rep in range(4):
+        for t in got:
+            t.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(got, want)):
+            assert torch.equal(a, b), (rep, k)
+        # eager calls of the same library on other positions between replays
+        other = _calls(x2t, y2t, vy, vx, prec)
+        torch.cuda.synchronize()
+        assert torch.isfinite(other[2]).all()

@@ -66,3 +66,20 @@ def test_radial_histogram_exact(dev):
     for nb in (1, 4, 50, 1000):
         c = ST.radial_histogram(xt, yt, nb).cpu().numpy()
         assert np.array_equal(c, S.radial_counts(x, y, nb)), nb
+
+
+def test_voronoi_degenerate_inputs(dev):
+    """One, two and three charges are all hull vertices (z = -2).  Charges
+    strictly between two others on a line have unbounded strip cells though
+    they are not hull vertices: z = -1 (the documented result for a cell the
+    largest square cannot hold), psi_6 = 0."""
+    cases = [
+        (np.array([0.1]), np.array([-0.2]), [-2]),
+        (np.array([0.1, -0.3]), np.array([0.2, 0.4]), [-2, -2]),
+        (np.array([0.0, 0.5, -0.4]), np.array([0.0, 0.1, 0.3]), [-2, -2, -2]),
+        (np.linspace(-0.8, 0.8, 5), 0.25 * np.linspace(-0.8, 0.8, 5), [-2, -1, -1, -1, -2]),
+    ]
+    for x, y, want in cases:
+        z, psi = ST.voronoi(torch.tensor(x, device=dev), torch.tensor(y, device=dev))
+        assert z.cpu().numpy().tolist() == want
+        assert np.all(psi.cpu().numpy() == 0.0)
