@@ -399,8 +399,8 @@ def main():
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the all-pairs pass shards by i-range across GPUs "
-              "(design in DESIGN.md) but no multi-GPU path is built; run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the all-pairs pass would shard by i-range across "
+              "GPUs, but no multi-GPU path is built; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
