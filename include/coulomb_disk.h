@@ -189,7 +189,10 @@ typedef struct {
  * Output pointers other than x_out/y_out may be NULL.  ws: at least
  * coulomb_workspace_bytes(CD_OP_RELAX, n, P, patch_ptr[P], opts->precision).
  * Reads a few per-round flags back to the host and synchronises the stream
- * before returning. */
+ * before returning.  The lock-step rounds are replayed from HIP graphs
+ * captured on a private stream that follows `stream` (environment variable
+ * CD_RELAX_GRAPH=0: the same kernels launched one by one, with identical
+ * results). */
 int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patches,
                      const int32_t* patch_ptr, const int32_t* active_idx,
                      const double* x_start, const double* y_start, const cd_relax_opts* opts,

@@ -1548,19 +1548,94 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 // Returns a CD status.
 static int g_last_rounds = 0;
 static bool g_trace = false;  // CD_RELAX_TRACE set: progress lines on stderr
+constexpr int kGraphRounds = 8;  // rounds per graph launch (the running count is read between)
+
+// The rounds of one relax call as HIP graphs: kGraphRounds rounds (model or
+// exact evaluation, then the update) are captured once per evaluation shape
+// on a private stream, which follows the caller's stream through events (a
+// caller's default stream cannot be captured), and replayed until no patch
+// runs.  The kernels and their arguments are those of the plain launches, so
+// the results are the same bit for bit.  CD_RELAX_GRAPH=0 selects the plain
+// launches; a graph that cannot be built falls back to them.
+struct RoundGraphs {
+  hipStream_t cs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  bool ok = false;
+  bool begin(hipStream_t st) {
+    const char* e = getenv("CD_RELAX_GRAPH");
+    if (e && e[0] == '0') return false;
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
+    if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
+      return false;
+    return ok = true;
+  }
+  int end(hipStream_t st) {  // the caller's stream waits for the private one
+    if (!ok) return CD_OK;
+    ok = false;
+    if (hipEventRecord(ev, cs) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess)
+      return CD_ERR_HIP;
+    return CD_OK;
+  }
+  ~RoundGraphs() {
+    for (hipGraphExec_t& x : ex)
+      if (x) (void)hipGraphExecDestroy(x);
+    if (ev) (void)hipEventDestroy(ev);
+    if (cs) {
+      (void)hipStreamSynchronize(cs);
+      (void)hipStreamDestroy(cs);
+    }
+  }
+};
 
 template <class EvalFn>
-static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, EvalFn eval) {
+static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn& eval) {
+  eval(s, shape);
+  if (hist32)
+    hipLaunchKernelGGL(k_update<float>, dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else
+    hipLaunchKernelGGL(k_update<double>, dim3(R.P), dim3(kUpd), 0, s, R.D);
+}
+
+// eval(stream, shape) enqueues one evaluation; shape(): 0 or 1, the
+// evaluation's launch shape for the current running count.
+template <class EvalFn, class ShapeFn>
+static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, RoundGraphs& G,
+                      EvalFn eval, ShapeFn shape) {
   RelaxDev& D = R.D;
   int32_t h_running = 0;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
+  if (!g_trace && G.begin(st)) {
+    hipStream_t cs = G.cs;
+    for (int r = 0; r < max_rounds; r += kGraphRounds) {
+      const int sh = shape();
+      if (!G.ex[sh]) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return CD_ERR_HIP;
+        for (int q = 0; q < kGraphRounds; ++q) launch_round(R, cs, hist32, sh, eval);
+        if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return CD_ERR_HIP;
+        const hipError_t ie = hipGraphInstantiate(&G.ex[sh], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+          G.ex[sh] = nullptr;
+          return CD_ERR_HIP;
+        }
+      }
+      g_last_rounds = r + kGraphRounds;
+      if (hipGraphLaunch(G.ex[sh], cs) != hipSuccess ||
+          hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, cs) !=
+              hipSuccess ||
+          hipStreamSynchronize(cs) != hipSuccess)
+        return CD_ERR_HIP;
+      R.running = h_running;
+      if (h_running <= 0) break;
+    }
+    return G.end(st);
+  }
   for (int r = 0; r < max_rounds; ++r) {
     g_last_rounds = r + 1;
-    eval();
-    if (hist32)
-      hipLaunchKernelGGL(k_update<float>, dim3(R.P), dim3(kUpd), 0, st, D);
-    else
-      hipLaunchKernelGGL(k_update<double>, dim3(R.P), dim3(kUpd), 0, st, D);
+    launch_round(R, st, hist32, shape(), eval);
     if ((r & 7) == 7) {
       if (hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
           hipSuccess)
@@ -1696,18 +1771,22 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   }
   hipLaunchKernelGGL(k_patch_geom, dim3(n_patches), dim3(256), 0, st, D);
   const dim3 eg((D.nblk + 3) / 4, R.splits), eb(256);
-  auto exact_grad = [&](int all) {
+  auto exact_grad_on = [&](int all, hipStream_t s) {
     RelaxDev E = D;
     E.eval_all = all;
-    hipLaunchKernelGGL(k_exact<kGrad>, eg, eb, 0, st, E);
-    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, E, (int)kGrad);
+    hipLaunchKernelGGL(k_exact<kGrad>, eg, eb, 0, s, E);
+    hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, s, E, (int)kGrad);
   };
+  auto exact_grad = [&](int all) { exact_grad_on(all, st); };
+  RoundGraphs graphs;
 
   if (o.max_iter == 0) {
     // evaluation only: the outputs describe the (projected) start positions
   } else if (o.precision == CD_FP64) {
     D.tol = o.gtol;
-    if ((rc = run_rounds(R, st, max_rounds, false, [&]() { exact_grad(0); }))) return rc;
+    if ((rc = run_rounds(R, st, max_rounds, false, graphs,
+                         [&](hipStream_t s, int) { exact_grad_on(0, s); }, []() { return 0; })))
+      return rc;
   } else {
     const double w = (o.halo_width > 0.0 ? o.halo_width : 4.0) * h;
     hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 0, R.hcount);
@@ -1727,24 +1806,28 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     Df.eval_all = 1;
     const int hb = (hp[n_patches] + 255) / 256;
     hipLaunchKernelGGL(k_model_prep, dim3(tb > hb ? tb : hb), dim3(256), 0, st, D, 1);
-    auto model = [&](int all) {
+    // 16-wave model blocks when the running patches hold fewer than 512
+    // blocks (estimated from the running count)
+    auto wide_shape = [&]() {
+      return (int)((int64_t)R.running * D.nblk < (int64_t)512 * n_patches);
+    };
+    auto model_on = [&](int all, hipStream_t s, int wide) {
       RelaxDev E = D;
       E.eval_all = all;
       // within the rounds k_update writes the FP32 coordinates of each trial
-      if (all) hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, st, E, 0);
+      if (all) hipLaunchKernelGGL(k_model_prep, dim3(tb), dim3(256), 0, s, E, 0);
       // the Hessian blocks (preconditioner) are evaluated at the expansion
       // point only and kept for the rest of the round
-      // blocks of running patches, estimated from the running count
-      const bool wide = (int64_t)R.running * D.nblk < (int64_t)512 * n_patches;
       if (all && wide)
-        hipLaunchKernelGGL((k_model<true, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, st, E);
+        hipLaunchKernelGGL((k_model<true, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, s, E);
       else if (all)
-        hipLaunchKernelGGL((k_model<true, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+        hipLaunchKernelGGL((k_model<true, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, s, E);
       else if (wide)
-        hipLaunchKernelGGL((k_model<false, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, st, E);
+        hipLaunchKernelGGL((k_model<false, kMWWide>), dim3(D.nblk), dim3(64 * kMWWide), 0, s, E);
       else
-        hipLaunchKernelGGL((k_model<false, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, st, E);
+        hipLaunchKernelGGL((k_model<false, kMW>), dim3(D.nblk), dim3(64 * kMW), 0, s, E);
     };
+    auto model = [&](int all) { model_on(all, st, wide_shape()); };
     // rounds: expand the far field exactly at z (one O(n_act N) FP64 pass);
     // the model gradient at its expansion point is the exact gradient, which
     // ends a patch when it meets gtol; otherwise minimise the model (FP32
@@ -1787,7 +1870,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       }
       if (hr == 0) break;
       D.ptol = ptol_ws;
-      rc = run_rounds(R, st, max_rounds, true, [&]() { model(0); });
+      rc = run_rounds(R, st, max_rounds, true, graphs,
+                      [&](hipStream_t s, int wide) { model_on(0, s, wide); }, wide_shape);
       D.ptol = nullptr;
       if (rc) return rc;
     }
