@@ -1043,9 +1043,25 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       if (h != R.held[a]) {
         R.held[a] = h;
         if (!s.init) {
+          // the charge's history into its new coordinates, keeping the
+          // tangential part of every pair: angle step s_t = t.s / r and
+          // angle-gradient change y_t = r t.y (t the unit tangent), and back
+          // to the Cartesian vectors s_t r t and (y_t / r) t on release
+          const double r = sqrt(px * px + py * py);
+          const double ux = -py / r, uy = px / r;
           for (int k = 0; k < m; ++k) {
             const size_t q = (size_t)k * R.ntot + a;
-            Sx[q] = Sy[q] = Yx[q] = Yy[q] = (HT)0;
+            const double s0 = Sx[q], s1 = Sy[q], y0 = Yx[q], y1 = Yy[q];
+            if (h) {
+              Sx[q] = (HT)((ux * s0 + uy * s1) / r);
+              Yx[q] = (HT)(r * (ux * y0 + uy * y1));
+              Sy[q] = Yy[q] = (HT)0;
+            } else {
+              Sx[q] = (HT)(r * s0 * ux);
+              Sy[q] = (HT)(r * s0 * uy);
+              Yx[q] = (HT)(y0 / r * ux);
+              Yy[q] = (HT)(y0 / r * uy);
+            }
           }
         }
         s_flag = 1;
@@ -1055,7 +1071,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     const double gi = block_max(gm, red);
     __syncthreads();
     if (s_flag && s.mem > 0) {
-      // entries were cleared: every rho again, eight pairs per pass over the
+      // entries were converted: every rho again, eight pairs per pass over the
       // actives and one many-value sum (thread j < 8 finishes pair 8h + j)
       const int M = s.mem;
       for (int h = 0; 8 * h < M; ++h) {
