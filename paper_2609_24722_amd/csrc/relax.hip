@@ -1177,43 +1177,102 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       for (int j = 0; j < kRegJ; ++j) {
         const int a = a0 + t + j * kUpd;
         const bool ok = kin && a < a1;
-        u0[j] = ok ? Sx[base + a] : (HT)0;
-        u1[j] = ok ? Sy[base + a] : (HT)0;
-        w0[j] = ok ? Yx[base + a] : (HT)0;
-        w1[j] = ok ? Yy[base + a] : (HT)0;
+        const size_t q = base + (size_t)min(a, a1 - 1);
+        const HT x0 = Sx[q], x1 = Sy[q], x2 = Yx[q], x3 = Yy[q];
+        u0[j] = ok ? x0 : (HT)0;
+        u1[j] = ok ? x1 : (HT)0;
+        w0[j] = ok ? x2 : (HT)0;
+        w1[j] = ok ? x3 : (HT)0;
       }
     };
-    if (kPre) load_pair(0, ux, uy, wx, wy);
-    for (int k = 0; k < s.mem; ++k) {
-      const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
-      const size_t base = (size_t)kk * R.ntot;
-      HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
-      if (kPre)
-        load_pair(k + 1, nux, nuy, nwx, nwy);
-      else
-        load_pair(k, ux, uy, wx, wy);
-      double v = 0.0;
-#pragma unroll
-      for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
-      for (int a = tail0; a < a1; a += kUpd)
-        v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
-      const double rk = s_rho[kk];  // read ahead of the reduction's barrier
-      const double al = rk * block_sum(v, red);
-      if (t == 0) s_alf[kk] = al;
+    // FP32 history: step k reduces pair k while pair k + 1 loads.  Two steps
+    // per loop trip, with the buffers' roles swapped, so no register copy
+    // waits on a load in flight.
+    // Raw loads at clamped, in-patch addresses (stored, finite values): no
+    // branch or select stands between a load and its use.  A pair outside
+    // the memory is loaded but never used; the elements past the patch end
+    // meet q = 0 in the sums and are masked (mk = 0) in the updates, so q
+    // stays 0 there.
+    auto load_vec = [&](const HT* A0, const HT* A1, int k, HT* v0, HT* v1) {
+      const bool kin = k >= 0 && k < s.mem;
+      const int sk = s.head - 1 - (kin ? k : 0);
+      const size_t base = (size_t)(sk < 0 ? sk + m : sk) * R.ntot;
 #pragma unroll
       for (int j = 0; j < kRegJ; ++j) {
-        qx[j] -= al * (double)wx[j];
-        qy[j] -= al * (double)wy[j];
-        if (kPre) {
-          ux[j] = nux[j];
-          uy[j] = nuy[j];
-          wx[j] = nwx[j];
-          wy[j] = nwy[j];
-        }
+        const size_t q = base + (size_t)min(a0 + t + j * kUpd, a1 - 1);
+        v0[j] = A0[q];
+        v1[j] = A1[q];
       }
-      for (int a = tail0; a < a1; a += kUpd) {
-        R.dx[a] -= al * (double)Yx[base + a];
-        R.dy[a] -= al * (double)Yy[base + a];
+    };
+    double mk[kRegJ];
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) mk[j] = a0 + t + j * kUpd < a1 ? 1.0 : 0.0;
+    if constexpr (kPre) {
+      HT a0s[kRegJ], a1s[kRegJ], a0y[kRegJ], a1y[kRegJ];
+      HT b0s[kRegJ], b1s[kRegJ], b0y[kRegJ], b1y[kRegJ];
+      auto step1 = [&](int k, HT* c0s, HT* c1s, HT* c0y, HT* c1y, HT* n0s, HT* n1s, HT* n0y,
+                       HT* n1y) {
+        const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
+        const size_t base = (size_t)kk * R.ntot;
+        load_vec(Sx, Sy, k + 1, n0s, n1s);
+        load_vec(Yx, Yy, k + 1, n0y, n1y);
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRegJ; ++j) v += (double)c0s[j] * qx[j] + (double)c1s[j] * qy[j];
+        for (int a = tail0; a < a1; a += kUpd)
+          v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
+        const double rk = s_rho[kk];  // read ahead of the reduction's barrier
+        const double al = rk * block_sum(v, red);
+        if (t == 0) s_alf[kk] = al;
+#pragma unroll
+        for (int j = 0; j < kRegJ; ++j) {
+          qx[j] -= al * (mk[j] * (double)c0y[j]);
+          qy[j] -= al * (mk[j] * (double)c1y[j]);
+        }
+        for (int a = tail0; a < a1; a += kUpd) {
+          R.dx[a] -= al * (double)Yx[base + a];
+          R.dy[a] -= al * (double)Yy[base + a];
+        }
+      };
+      load_vec(Sx, Sy, 0, a0s, a1s);
+      load_vec(Yx, Yy, 0, a0y, a1y);
+      for (int k = 0; k < s.mem; k += 2) {
+        step1(k, a0s, a1s, a0y, a1y, b0s, b1s, b0y, b1y);
+        if (k + 1 < s.mem) step1(k + 1, b0s, b1s, b0y, b1y, a0s, a1s, a0y, a1y);
+      }
+    } else {
+      if (kPre) load_pair(0, ux, uy, wx, wy);
+      for (int k = 0; k < s.mem; ++k) {
+        const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
+        const size_t base = (size_t)kk * R.ntot;
+        HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+        if (kPre)
+          load_pair(k + 1, nux, nuy, nwx, nwy);
+        else
+          load_pair(k, ux, uy, wx, wy);
+        double v = 0.0;
+  #pragma unroll
+        for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
+        for (int a = tail0; a < a1; a += kUpd)
+          v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
+        const double rk = s_rho[kk];  // read ahead of the reduction's barrier
+        const double al = rk * block_sum(v, red);
+        if (t == 0) s_alf[kk] = al;
+  #pragma unroll
+        for (int j = 0; j < kRegJ; ++j) {
+          qx[j] -= al * (double)wx[j];
+          qy[j] -= al * (double)wy[j];
+          if (kPre) {
+            ux[j] = nux[j];
+            uy[j] = nuy[j];
+            wx[j] = nwx[j];
+            wy[j] = nwy[j];
+          }
+        }
+        for (int a = tail0; a < a1; a += kUpd) {
+          R.dx[a] -= al * (double)Yx[base + a];
+          R.dy[a] -= al * (double)Yy[base + a];
+        }
       }
     }
     // the preconditioner goes through memory (a loop, not unrolled: its
@@ -1241,37 +1300,72 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         qy[j] = R.dy[a];
       }
     }
-    if (kPre) load_pair(s.mem - 1, ux, uy, wx, wy);
-    for (int k = s.mem - 1; k >= 0; --k) {
-      const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
-      const size_t base = (size_t)kk * R.ntot;
-      HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
-      if (kPre)
-        load_pair(k - 1, nux, nuy, nwx, nwy);
-      else
-        load_pair(k, ux, uy, wx, wy);
-      double v = 0.0;
+    if constexpr (kPre) {
+      HT a0s[kRegJ], a1s[kRegJ], a0y[kRegJ], a1y[kRegJ];
+      HT b0s[kRegJ], b1s[kRegJ], b0y[kRegJ], b1y[kRegJ];
+      auto step2 = [&](int k, HT* c0s, HT* c1s, HT* c0y, HT* c1y, HT* n0s, HT* n1s, HT* n0y,
+                       HT* n1y) {
+        const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
+        const size_t base = (size_t)kk * R.ntot;
+        load_vec(Sx, Sy, k - 1, n0s, n1s);
+        load_vec(Yx, Yy, k - 1, n0y, n1y);
+        double v = 0.0;
 #pragma unroll
-      for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
-      for (int a = tail0; a < a1; a += kUpd)
-        v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
-      const double rk = s_rho[kk];
-      const double be = rk * block_sum(v, red);
-      const double coef = s_alf[kk] - be;
+        for (int j = 0; j < kRegJ; ++j) v += (double)c0y[j] * qx[j] + (double)c1y[j] * qy[j];
+        for (int a = tail0; a < a1; a += kUpd)
+          v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
+        const double rk = s_rho[kk];
+        const double be = rk * block_sum(v, red);
+        const double coef = s_alf[kk] - be;
 #pragma unroll
-      for (int j = 0; j < kRegJ; ++j) {
-        qx[j] += coef * (double)ux[j];
-        qy[j] += coef * (double)uy[j];
-        if (kPre) {
-          ux[j] = nux[j];
-          uy[j] = nuy[j];
-          wx[j] = nwx[j];
-          wy[j] = nwy[j];
+        for (int j = 0; j < kRegJ; ++j) {
+          qx[j] += coef * (mk[j] * (double)c0s[j]);
+          qy[j] += coef * (mk[j] * (double)c1s[j]);
         }
+        for (int a = tail0; a < a1; a += kUpd) {
+          R.dx[a] += coef * (double)Sx[base + a];
+          R.dy[a] += coef * (double)Sy[base + a];
+        }
+      };
+      load_vec(Sx, Sy, s.mem - 1, a0s, a1s);
+      load_vec(Yx, Yy, s.mem - 1, a0y, a1y);
+      for (int k = s.mem - 1; k >= 0; k -= 2) {
+        step2(k, a0s, a1s, a0y, a1y, b0s, b1s, b0y, b1y);
+        if (k - 1 >= 0) step2(k - 1, b0s, b1s, b0y, b1y, a0s, a1s, a0y, a1y);
       }
-      for (int a = tail0; a < a1; a += kUpd) {
-        R.dx[a] += coef * (double)Sx[base + a];
-        R.dy[a] += coef * (double)Sy[base + a];
+    } else {
+      if (kPre) load_pair(s.mem - 1, ux, uy, wx, wy);
+      for (int k = s.mem - 1; k >= 0; --k) {
+        const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
+        const size_t base = (size_t)kk * R.ntot;
+        HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+        if (kPre)
+          load_pair(k - 1, nux, nuy, nwx, nwy);
+        else
+          load_pair(k, ux, uy, wx, wy);
+        double v = 0.0;
+  #pragma unroll
+        for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
+        for (int a = tail0; a < a1; a += kUpd)
+          v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
+        const double rk = s_rho[kk];
+        const double be = rk * block_sum(v, red);
+        const double coef = s_alf[kk] - be;
+  #pragma unroll
+        for (int j = 0; j < kRegJ; ++j) {
+          qx[j] += coef * (double)ux[j];
+          qy[j] += coef * (double)uy[j];
+          if (kPre) {
+            ux[j] = nux[j];
+            uy[j] = nuy[j];
+            wx[j] = nwx[j];
+            wy[j] = nwy[j];
+          }
+        }
+        for (int a = tail0; a < a1; a += kUpd) {
+          R.dx[a] += coef * (double)Sx[base + a];
+          R.dy[a] += coef * (double)Sy[base + a];
+        }
       }
     }
 #pragma unroll
