@@ -1275,30 +1275,25 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         }
       }
     }
-    // the preconditioner goes through memory (a loop, not unrolled: its
-    // temporaries would not fit beside the register-held vector)
+    // the preconditioner, in registers for the register-held elements and
+    // in memory for the tail
 #pragma unroll
     for (int j = 0; j < kRegJ; ++j) {
       const int a = a0 + t + j * kUpd;
       if (a < a1) {
-        R.dx[a] = qx[j];
-        R.dy[a] = qy[j];
+        double r0, r1;
+        apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
+                   qx[j], qy[j], r0, r1);
+        qx[j] = r0;
+        qy[j] = r1;
       }
     }
-    for (int a = a0 + t; a < a1; a += kUpd) {
+    for (int a = tail0; a < a1; a += kUpd) {
       double r0, r1;
       apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
                  R.dx[a], R.dy[a], r0, r1);
       R.dx[a] = r0;
       R.dy[a] = r1;
-    }
-#pragma unroll
-    for (int j = 0; j < kRegJ; ++j) {
-      const int a = a0 + t + j * kUpd;
-      if (a < a1) {
-        qx[j] = R.dx[a];
-        qy[j] = R.dy[a];
-      }
     }
     if constexpr (kPre) {
       HT a0s[kRegJ], a1s[kRegJ], a0y[kRegJ], a1y[kRegJ];
