@@ -1150,8 +1150,9 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   // in R.dx, R.dy, touched only by their own thread, inside the same steps.
   // Each thread sums its actives in increasing order, then the workgroup sum.
   __syncthreads();
+  const int tail0 = a0 + t + kRegJ * kUpd;
+  double dxr[kRegJ], dyr[kRegJ];  // the direction of the register-held elements
   {
-    const int tail0 = a0 + t + kRegJ * kUpd;
     double qx[kRegJ], qy[kRegJ];
 #pragma unroll
     for (int j = 0; j < kRegJ; ++j) {
@@ -1365,18 +1366,30 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     }
 #pragma unroll
     for (int j = 0; j < kRegJ; ++j) {
-      const int a = a0 + t + j * kUpd;
-      if (a < a1) {
-        R.dx[a] = qx[j];
-        R.dy[a] = qy[j];
-      }
+      dxr[j] = qx[j];
+      dyr[j] = qy[j];
     }
   }
   // d = -H g; fall back to scaled steepest descent if not a descent direction
   // (the step length bound dm is taken in the same pass; the rare steepest
-  // descent fallback takes it again)
+  // descent fallback takes it again).  Register-held elements first, then
+  // the tail: the actives in increasing order, as everywhere.
   double dg = 0.0, dm = 0.0;
-  for (int a = a0 + t; a < a1; a += kUpd) {
+#pragma unroll
+  for (int j = 0; j < kRegJ; ++j) {
+    const int a = a0 + t + j * kUpd;
+    if (a < a1) {
+      double c0, c1;
+      const bool h = R.held[a];
+      coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      const double d0 = -dxr[j], d1 = -dyr[j];
+      dxr[j] = d0;
+      dyr[j] = d1;
+      dg += d0 * c0 + d1 * c1;
+      dm = fmax(dm, h ? fabs(d0) : sqrt(d0 * d0 + d1 * d1));
+    }
+  }
+  for (int a = tail0; a < a1; a += kUpd) {
     double c0, c1;
     const bool h = R.held[a];
     coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
@@ -1401,21 +1414,35 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       dm = fmax(dm, h ? fabs(r0) : sqrt(r0 * r0 + r1 * r1));
     }
     dm = block_max(dm, red);
+#pragma unroll
+    for (int j = 0; j < kRegJ; ++j) {
+      const int a = a0 + t + j * kUpd;
+      if (a < a1) {
+        dxr[j] = R.dx[a];
+        dyr[j] = R.dy[a];
+      }
+    }
   }
   const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
   s.alpha = 1.0;
-  for (int a = a0 + t; a < a1; a += kUpd) {
-    R.dx[a] *= sc;
-    R.dy[a] *= sc;
+  auto step_to = [&](int a, double d0, double d1) {
+    R.dx[a] = d0;
+    R.dy[a] = d1;
     double nx, ny;
-    take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], 1.0, nx, ny, R.pin[a], R.sigma);
+    take_step(R.held[a], R.zx[a], R.zy[a], d0, d1, 1.0, nx, ny, R.pin[a], R.sigma);
     R.tx[a] = nx;
     R.ty[a] = ny;
     if (R.a32x) {
       R.a32x[a] = (float)(nx - s.cx);
       R.a32y[a] = (float)(ny - s.cy);
     }
+  };
+#pragma unroll
+  for (int j = 0; j < kRegJ; ++j) {
+    const int a = a0 + t + j * kUpd;
+    if (a < a1) step_to(a, dxr[j] * sc, dyr[j] * sc);
   }
+  for (int a = tail0; a < a1; a += kUpd) step_to(a, R.dx[a] * sc, R.dy[a] * sc);
   if (t == 0) R.st[p] = s;
 }
 
