@@ -941,19 +941,21 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   // pred = grad(z).s, dpt = grad(zt).s; a held charge's step is the angle
   // alpha*d (its Cartesian displacement has a second-order radial part that
   // the large wall reaction would weigh), a free charge's is zt - z
+  // (every value is loaded before the held test selects the formula, so
+  // the loads of an active go out together)
   double e = 0.0, pr = 0.0, pt = 0.0;
   for (int a = a0 + t; a < a1; a += kUpd) {
     e += R.eterm[a];
     if (s.init) continue;
-    if (R.held[a]) {
-      const double st = s.alpha * R.dx[a];
-      pr += (-R.gx[a] * R.zy[a] + R.gy[a] * R.zx[a]) * st;
-      pt += (-R.hgx[a] * R.ty[a] + R.hgy[a] * R.tx[a]) * st;
-    } else {
-      const double ddx = R.tx[a] - R.zx[a], ddy = R.ty[a] - R.zy[a];
-      pr += R.gx[a] * ddx + R.gy[a] * ddy;
-      pt += R.hgx[a] * ddx + R.hgy[a] * ddy;
-    }
+    const int h = R.held[a];
+    const double gx = R.gx[a], gy = R.gy[a], hgx = R.hgx[a], hgy = R.hgy[a];
+    const double zx = R.zx[a], zy = R.zy[a], tx = R.tx[a], ty = R.ty[a], dx = R.dx[a];
+    const double st = s.alpha * dx;
+    const double ddx = tx - zx, ddy = ty - zy;
+    const double prh = (-gx * zy + gy * zx) * st, pth = (-hgx * ty + hgy * tx) * st;
+    const double prf = gx * ddx + gy * ddy, ptf = hgx * ddx + hgy * ddy;
+    pr += h ? prh : prf;
+    pt += h ? pth : ptf;
   }
   block_sum3(e, pr, pt, red);
   const double Et = e;
@@ -991,16 +993,13 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       const int k = s.head;
       for (int a = a0 + t; a < a1; a += kUpd) {
         const bool h = R.held[a];
-        double s0, s1, c0, c1, n0, n1;
-        if (h) {
-          s0 = s.alpha * R.dx[a];
-          s1 = 0.0;
-        } else {
-          s0 = R.tx[a] - R.zx[a];
-          s1 = R.ty[a] - R.zy[a];
-        }
-        coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
-        coord_grad(h, R.tx[a], R.ty[a], R.hgx[a], R.hgy[a], n0, n1);
+        const double zx = R.zx[a], zy = R.zy[a], tx = R.tx[a], ty = R.ty[a], dx = R.dx[a];
+        const double gx = R.gx[a], gy = R.gy[a], hgx = R.hgx[a], hgy = R.hgy[a];
+        double c0, c1, n0, n1;
+        const double s0 = h ? s.alpha * dx : tx - zx;
+        const double s1 = h ? 0.0 : ty - zy;
+        coord_grad(h, zx, zy, gx, gy, c0, c1);
+        coord_grad(h, tx, ty, hgx, hgy, n0, n1);
         // the pair as stored (rounded to HT), so that rho matches the vectors
         const HT hs0 = (HT)s0, hs1 = (HT)s1, hy0 = (HT)(n0 - c0), hy1 = (HT)(n1 - c1);
         const size_t q = (size_t)k * R.ntot + a;
@@ -1008,11 +1007,10 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         Sy[q] = hs1;
         Yx[q] = hy0;
         Yy[q] = hy1;
-        s0 = hs0;
-        s1 = hs1;
+        const double u0 = hs0, u1 = hs1;
         const double y0 = hy0, y1 = hy1;
-        syp += s0 * y0 + s1 * y1;
-        ssp += s0 * s0 + s1 * s1;
+        syp += u0 * y0 + u1 * y1;
+        ssp += u0 * u0 + u1 * u1;
         yyp += y0 * y0 + y1 * y1;
       }
       block_sum3(syp, ssp, yyp, red);
