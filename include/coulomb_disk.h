@@ -46,7 +46,8 @@ enum {
   CD_ERR_WORKSPACE = -2,
   CD_ERR_HIP = -3,
   CD_ERR_DOMAIN = -4,
-  CD_ERR_CAPACITY = -5
+  CD_ERR_CAPACITY = -5,
+  CD_ERR_SCRATCH = -6
 };
 
 /* operation selectors for coulomb_workspace_bytes */
@@ -84,6 +85,23 @@ int coulomb_energy(const double* x, const double* y, int64_t n, int precision,
  * energy: fx[n], fy[n]; e_total (1 double) may be NULL. */
 int coulomb_forces(const double* x, const double* y, int64_t n, int precision, double* fx,
                    double* fy, double* e_total, void* ws, size_t ws_bytes, void* stream);
+
+/* Allocation-free coulomb_forces, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as coulomb_forces without
+ * ws/ws_bytes: the scratch is a fixed 64 MiB region inside the library,
+ * one per device, held from its first use on that device until the process
+ * ends.  CD_MIXED batches the symmetric pass's chunks so that their partial
+ * sums fit (more, smaller batches than coulomb_forces at large n; the sums
+ * then run in another order, differences at FP64 rounding level).  Sizes
+ * that do not fit return CD_ERR_SCRATCH before anything is enqueued
+ * (every n up to 830,720 fits on CD_FP64, up to 706,304 on CD_MIXED).  Every call on
+ * one device shares that device's region: calls that overlap on a device
+ * (two streams, threads or graph replays in flight) race; serialise them.
+ * Nothing needs clearing between calls.  Launches kernels only (no copy,
+ * memset or synchronisation), so it can be captured in a HIP graph. */
+int coulomb_forces_noalloc(const double* x, const double* y, int64_t n, int precision,
+                           double* fx, double* fy, double* e_total, void* stream);
 
 /* Riesz-s generalisation of Eq. 2 (the paper states its result in Riesz
  * terms, Sec. III.E): *e_total = sum_{i<j} r_ij^(-s) (nullable) and

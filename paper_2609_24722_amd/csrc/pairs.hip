@@ -977,7 +977,7 @@ static int tuned_shape(int op, int64_t n) {
 }
 
 // ---------------------------------------------------------------- planning --
-bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape) {
+bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape, int max_cb) {
   if (n64 < 1 || n64 > (int64_t)1 << 26) return false;
   if (precision != CD_FP64 && precision != CD_MIXED) return false;
   const int n = (int)n64;
@@ -1009,7 +1009,9 @@ bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shap
     size_t cb = kSymBatchBytes / per;
     if (cb < 1) cb = 1;
     if (cb > (size_t)kSymBatchMax) cb = kSymBatchMax;
+    if (max_cb > 0 && cb > (size_t)max_cb) cb = max_cb;
     P.Cb = cb < (size_t)P.C ? (int)cb : P.C;
+    P.chunk_bytes = per;
   } else {
     // enough waves to fill 256 CUs several times over
     int sp = (16384 + P.nb - 1) / P.nb;
@@ -1281,6 +1283,10 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
   return cd::relax_workspace_bytes(op, n, n_patches, total_active, precision);
 }
 
+}  // extern "C"
+
+namespace cd {
+
 static int check_ws(int op, int64_t n, int precision, void* ws, size_t ws_bytes, Plan& P,
                     int shape = -1) {
   if (!ws) return CD_ERR_WORKSPACE;
@@ -1310,14 +1316,10 @@ static int energy_impl(const double* x, const double* y, int64_t n, int precisio
   return hip_status(hipGetLastError());
 }
 
-static int forces_impl(const double* x, const double* y, int64_t n, int precision, double* fx,
-                       double* fy, double* e_total, void* ws, size_t ws_bytes, hipStream_t st,
-                       int shape) {
-  if (!x || !y || !fx || !fy) return CD_ERR_INVALID_ARG;
-  Plan P;
-  int rc = check_ws(CD_OP_FORCES, n, precision, ws, ws_bytes, P, shape);
+static int forces_run(const Plan& P, const double* x, const double* y, int precision,
+                      double* fx, double* fy, double* e_total, hipStream_t st) {
+  int rc = stage(P, x, y, nullptr, nullptr, st);
   if (rc) return rc;
-  if ((rc = stage(P, x, y, nullptr, nullptr, st))) return rc;
   if (precision == CD_MIXED) {
     run_sym<kForces, false>(P, st, fx, fy, e_total);
   } else {
@@ -1325,6 +1327,53 @@ static int forces_impl(const double* x, const double* y, int64_t n, int precisio
     if (e_total) sum_blocks(P.eblk, P.nred, e_total, st);
   }
   return hip_status(hipGetLastError());
+}
+
+static int forces_impl(const double* x, const double* y, int64_t n, int precision, double* fx,
+                       double* fy, double* e_total, void* ws, size_t ws_bytes, hipStream_t st,
+                       int shape) {
+  if (!x || !y || !fx || !fy) return CD_ERR_INVALID_ARG;
+  Plan P;
+  int rc = check_ws(CD_OP_FORCES, n, precision, ws, ws_bytes, P, shape);
+  if (rc) return rc;
+  return forces_run(P, x, y, precision, fx, fy, e_total, st);
+}
+
+// Plan of a forces call inside cap bytes: the default plan, or the same
+// shape with fewer chunks per batch.
+static int plan_fixed(int64_t n, int precision, char* base, size_t cap, Plan& P) {
+  const int shape = precision == CD_MIXED ? tuned_shape(CD_OP_FORCES, n) : -1;
+  if (!make_plan(CD_OP_FORCES, n, precision, nullptr, P, shape)) return CD_ERR_INVALID_ARG;
+  int cb = P.Cb;
+  if (P.total > cap) {
+    if (precision != CD_MIXED || P.Cb <= 1) return CD_ERR_CAPACITY;
+    const size_t over = P.total - cap;  // chunks to drop, rounded up
+    const size_t drop = (over + P.chunk_bytes - 1) / P.chunk_bytes;
+    if (drop >= (size_t)P.Cb) return CD_ERR_CAPACITY;
+    cb = P.Cb - (int)drop;
+    // the carve aligns each piece, so step down until the plan fits
+    for (;; --cb) {
+      if (cb < 1) return CD_ERR_CAPACITY;
+      make_plan(CD_OP_FORCES, n, precision, nullptr, P, shape, cb);
+      if (P.total <= cap) break;
+    }
+  }
+  if (base) make_plan(CD_OP_FORCES, n, precision, base, P, shape, cb);
+  return CD_OK;
+}
+
+int forces_fixed_fits(int64_t n, int precision, size_t cap) {
+  Plan P;
+  return plan_fixed(n, precision, nullptr, cap, P);
+}
+
+int forces_fixed(const double* x, const double* y, int64_t n, int precision, double* fx,
+                 double* fy, double* e_total, char* base, size_t cap, hipStream_t st) {
+  if (!x || !y || !fx || !fy || !base) return CD_ERR_INVALID_ARG;
+  Plan P;
+  const int rc = plan_fixed(n, precision, base, cap, P);
+  if (rc) return rc;
+  return forces_run(P, x, y, precision, fx, fy, e_total, st);
 }
 
 static int riesz_impl(const double* x, const double* y, int64_t n, double rs, int precision,
@@ -1357,6 +1406,10 @@ static int hvp_impl(const double* x, const double* y, const double* vx, const do
   else run_one64<kHvp>(P, st, hx, hy);
   return hip_status(hipGetLastError());
 }
+
+}  // namespace cd
+
+extern "C" {
 
 int coulomb_energy(const double* x, const double* y, int64_t n, int precision, double* e_total,
                    double* e_local, void* ws, size_t ws_bytes, void* stream) {
@@ -1460,6 +1513,7 @@ const char* coulomb_status_string(int code) {
     case CD_ERR_HIP: return "HIP runtime error";
     case CD_ERR_DOMAIN: return "positions outside the domain";
     case CD_ERR_CAPACITY: return "output capacity too small (sizes reported)";
+    case CD_ERR_SCRATCH: return "sizes exceed the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -41,6 +41,7 @@ struct Plan {
   int shape = 0;                           // symmetric pass launch shape (index)
   int W = 0, L = 0, C = 0, G = 0, S = 0;  // symmetric pass
   int Cb = 0, mj = 0;                     // chunks per batch, j slots per chunk
+  size_t chunk_bytes = 0;                 // partial sums of one chunk (symmetric pass)
   int splits = 0, jb = 0;                 // one-sided pass
   int nred = 0;                           // reduction workgroups
   // workspace pieces
@@ -60,7 +61,20 @@ struct Plan {
 
 // shape: index into the symmetric pass's list of launch shapes (out of
 // range: the default); the entry points pass the one coulomb_autotune chose.
-bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape = -1);
+// max_cb > 0 caps the chunks per batch of the symmetric pass (smaller
+// scratch, more batches).
+bool make_plan(int op, int64_t n64, int precision, char* base, Plan& P, int shape = -1,
+               int max_cb = 0);
+
+// Forces and energy (coulomb_forces) with the scratch carved from a fixed
+// region [base, base + cap) (base 256-byte aligned): the symmetric pass's
+// chunks are batched so that their partial sums fit.  Returns
+// CD_ERR_CAPACITY, before anything is enqueued, when not even one chunk per
+// batch fits.
+int forces_fixed(const double* x, const double* y, int64_t n, int precision, double* fx,
+                 double* fy, double* e_total, char* base, size_t cap, hipStream_t st);
+// The same plan test alone (host only): CD_OK if the call fits in cap bytes.
+int forces_fixed_fits(int64_t n, int precision, size_t cap);
 int stage(const Plan& P, const double* x, const double* y, const double* vx, const double* vy,
           hipStream_t st);
 

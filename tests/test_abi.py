@@ -112,3 +112,16 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0
+
+
+def test_noalloc_refuses_sizes_beyond_its_scratch(L):
+    # refused on the host before anything is enqueued (the first n past the fixed
+    # scratch on each path); smaller sizes reach the GPU and are GPU tests
+    f = L.coulomb_forces_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_int] + [ctypes.c_void_p] * 4
+    d = ctypes.c_void_p(256)
+    assert f(d, d, 706305, 1, d, d, None, None) == -6
+    assert f(d, d, 830721, 0, d, d, None, None) == -6
+    assert f(d, d, 1 << 27, 0, d, d, None, None) == -1   # beyond any plan
+    assert f(None, d, 10, 0, d, d, None, None) == -1
