@@ -186,7 +186,35 @@ typedef struct {
   const int32_t* boundary;   /* device int32 [n] or NULL: nonzero marks a boundary
                                 charge, pinned to the unit circle (it moves only
                                 along it); starts are projected accordingly */
+  /* Truncated-Newton polish (the benchmark spec's HVP-driven FP64 polish): below
+   * newton_tol a patch takes Newton steps -- preconditioned CG (block-Jacobi:
+   * each charge's own 2x2 Hessian block) on the tangent-space Hessian of E_sub
+   * at the current point, in optimisation coordinates (held charges: their
+   * angle, with the circle's curvature term), stopped at non-positive
+   * curvature, at a residual inf-norm of cg_eta times the gradient's (but not
+   * below gtol / 10) or after max_polish_iter iterations; then the same line
+   * search as an L-BFGS step (a failed one falls back to L-BFGS).  The
+   * Hessian products are FP64 pairs over the patch's actives plus each
+   * charge's exact block.  CD_MIXED takes one Newton step per exact
+   * expansion of the far field (from the expansion point, where the model's
+   * Hessian is the exact one); CD_FP64 takes them back to back. */
+  int32_t polish;            /* CD_POLISH_NEWTON, CD_POLISH_LBFGS (L-BFGS to the end) or
+                                CD_POLISH_DEFAULT: Newton on CD_FP64, L-BFGS on CD_MIXED
+                                (the faster of the two on each path) */
+  int32_t max_polish_iter;   /* CG iterations per Newton step (0 = 500) */
+  double newton_tol;         /* on the exact reduced gradient's inf-norm (0 = 3e-2 / h^2
+                                on CD_FP64, 3e-5 / h^2 on CD_MIXED; h the mean spacing
+                                sqrt(2 pi / (sqrt(3) n))) */
+  double cg_eta;             /* relative CG residual target, fixed; 0 = 1e-2 on CD_FP64,
+                                adaptive on CD_MIXED: 0.1 for a first Newton step, then
+                                0.9 (g_k / g_{k-1})^2 within [1e-8, 0.1]
+                                (Eisenstat-Walker), and a second step that fails to
+                                halve the gradient returns the patch to L-BFGS */
+  int32_t* polish_stats;     /* device int32 [2P] or NULL: accepted Newton steps and CG
+                                iterations per patch */
 } cd_relax_opts;
+
+enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
 
 /* Relax every patch of the batch (Sec. II.C step 4) against the frozen
  * snapshot (x, y)[n]: minimise E_sub = sum_{i in A} e_i (Eqs. 6-7, 1/2 on
@@ -200,8 +228,8 @@ typedef struct {
  *   dE[P]: E_sub(relaxed) - E_sub(snapshot), exact FP64 pair differences.
  *   e_sub[P]: exact FP64 E_sub at the relaxed positions.
  *   gtan_inf[P]: inf-norm of the exact FP64 reduced gradient there.
- *   iters[2P]: accepted L-BFGS iterations (all stages) and exact FP64
- *     evaluations per patch.
+ *   iters[2P]: accepted iterations (L-BFGS and Newton steps, all stages)
+ *     and exact FP64 evaluations per patch.
  *   status[P]: 0 converged (gtan_inf <= gtol), 1 iteration cap, 2 line search
  *     failed, 3 non-finite.
  * Output pointers other than x_out/y_out may be NULL.  ws: at least

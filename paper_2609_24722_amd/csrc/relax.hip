@@ -142,6 +142,11 @@ enum PStatus {
   kDone = 5            // exact reduced gradient met the tolerance (mixed path)
 };
 enum Eval { kEvalExact = 0, kEvalModel32 = 1, kEvalModel64 = 2 };
+// What the next round does for a running patch: evaluate a trial point and
+// accept or shorten it (kPhaseStep), or one CG iteration of a Newton step
+// (kPhaseCG: the product of the tangent Hessian with the CG direction, then
+// the CG update).
+enum Phase { kPhaseStep = 0, kPhaseCG = 1 };
 
 struct PState {
   double E, Et;      // objective at z and at the trial zt (current evaluator)
@@ -151,7 +156,17 @@ struct PState {
   double cx, cy;     // patch centre (box centre of the snapshot actives)
   int it, mem, head, status, init, total_it, exact_evals, evals;
   int use32;         // mixed path: this round's model uses FP32 pairs
-  int pad;
+  int newton;        // truncated-Newton polish: directions from CG on the tangent Hessian
+  int phase;         // Phase
+  int cg_it;         // CG iterations of the current Newton step
+  int newton_steps;  // accepted Newton steps (all rounds)
+  int cg_total;      // CG iterations (all rounds)
+  int nfail;         // Newton steps that did not halve the reduced gradient
+  int newton_off;    // Newton mode given up for this patch (L-BFGS to the end)
+  double rz;         // CG: r . M^-1 r of the current residual
+  double cg_target;  // CG: the step ends when the residual's inf-norm is below this
+  double gnewt;      // reduced gradient at the start of the last Newton step (0: none)
+  double eta;        // relative CG target of the last Newton step
 };
 
 struct RelaxDev {
@@ -201,6 +216,16 @@ struct RelaxDev {
   int32_t* ptr_w;          // [P+1] device copy of the patch offsets (in the workspace)
   double* ptol;            // [P] per-patch stage tolerance (null: tol)
   int32_t* err;            // [1] argument error found on the device
+  // truncated-Newton polish: CG iterate x, residual r, direction d (all in
+  // optimisation coordinates), the product q = H_t d, and d in Cartesian
+  // form w (held charge: d_0 (-y, x); free: d)
+  double *cgx, *cgy, *crx, *cry, *cdx, *cdy, *cqx, *cqy, *cwx, *cwy;
+  int polish;              // directions of patches in Newton mode come from CG
+  int max_cg;              // CG iterations per Newton step
+  double newton_tol;       // Newton mode below this exact reduced gradient
+  double cg_eta;           // CG target: cg_eta * |g|inf of the step's start
+  double gtol;             // the call's tolerance on the exact reduced gradient
+  int32_t* pstats;         // [2P] or null: Newton steps and CG iterations per patch
 };
 
 // ------------------------------------------------------------ setup kernels --
@@ -367,7 +392,8 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   if (wb >= R.nblk) return;
   const int2 bk = R.blk[wb];
   const int p = bk.x;
-  if (MODE == kGrad && !R.eval_all && R.st[p].status != kRunning) return;
+  if (MODE == kGrad && !R.eval_all && (R.st[p].status != kRunning || R.st[p].phase == kPhaseCG))
+    return;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int a = bk.y + lane;
   const bool ok = a < a1;
@@ -614,7 +640,8 @@ __global__ __launch_bounds__(64 * MW) void k_model(RelaxDev R) {
   const int2 bk = R.blk[wb];
   const int p = bk.x;
   const PState& st = R.st[p];
-  if (!R.eval_all && st.status != kRunning) return;  // the same for the whole workgroup
+  // the same for the whole workgroup; a patch in its CG phase has no trial
+  if (!R.eval_all && (st.status != kRunning || st.phase == kPhaseCG)) return;
   const bool use32 = st.use32;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
@@ -693,6 +720,75 @@ __global__ void k_model_prep(RelaxDev R, int halo_too) {
     R.h64y[a] = R.y[j];
     R.h32x[a] = (float)(R.x[j] - s.cx);
     R.h32y[a] = (float)(R.y[j] - s.cy);
+  }
+}
+
+// ------------------------------------------------- truncated-Newton product --
+// q = H_t d for every patch in its CG phase (truncated-Newton polish): the
+// Hessian of E_sub at z on the tangent space of the wall, applied to the CG
+// direction d.  With w the Cartesian form of d,
+//   (H w)_i = B_i w_i - sum_{j in A, j != i} K(z_i - z_j) w_j,
+// K(r) = (3 r r^T - |r|^2 I) / |r|^5, where B_i = sum_{j != i} K(z_i - z_j)
+// over every other charge is the charge's own 2x2 block: exact FP64 at z,
+// written by the exact evaluation at z (plain path) or by the model
+// evaluation at its expansion point z (mixed path: there the far field's
+// quadratic carries the exact Hessian).  A held charge's coordinate is its
+// angle, with tangent t = (-y, x): its component is t . (H w)_i - (g_i . z_i)
+// d_i (the circle's curvature), a free charge's (H w)_i.  FP64 pairs.
+// Workgroup layout as k_model: MW waves split the patch's actives into
+// ranges cut at multiples of 64; their sums are combined in wave order.
+template <int MW>
+__global__ __launch_bounds__(64 * MW) void k_cg_hvp(RelaxDev R) {
+  __shared__ double part[MW][2][64];
+  const int wb = blockIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wb >= R.nblk) return;
+  const int2 bk = R.blk[wb];
+  const int p = bk.x;
+  const PState& st = R.st[p];
+  if (st.status != kRunning || st.phase != kPhaseCG) return;  // uniform in the workgroup
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  const int na = a1 - a0;
+  const int per = ((na + MW - 1) / MW + 63) & ~63;
+  const int j0 = min(na, w * per), j1 = min(na, j0 + per);
+  const int a = bk.y + lane;
+  const bool ok = a < a1;
+  const int ac = ok ? a : a1 - 1;
+  const double xi = R.zx[ac], yi = R.zy[ac];
+  double Q0 = 0.0, Q1 = 0.0;
+#pragma unroll 4
+  for (int b = a0 + j0; b < a0 + j1; ++b) {
+    const double dx = xi - R.zx[b], dy = yi - R.zy[b];
+    const double wx = R.cwx[b], wy = R.cwy[b];
+    const double r2 = __builtin_fma(dx, dx, dy * dy);
+    double inv = rsqrt64(r2);
+    inv = (b == ac) ? 0.0 : inv;
+    const double i3 = inv * inv * inv;
+    const double sc = 3.0 * i3 * inv * inv * __builtin_fma(dx, wx, dy * wy);
+    Q0 += __builtin_fma(dx, sc, -wx * i3);
+    Q1 += __builtin_fma(dy, sc, -wy * i3);
+  }
+  part[w][0][lane] = Q0;
+  part[w][1][lane] = Q1;
+  __syncthreads();
+  if (w != 0 || !ok) return;
+  Q0 = Q1 = 0.0;
+  for (int q = 0; q < MW; ++q) {
+    Q0 += part[q][0][lane];
+    Q1 += part[q][1][lane];
+  }
+  const double wx = R.cwx[a], wy = R.cwy[a];
+  const double hx = R.kxx[a] * wx + R.kxy[a] * wy - Q0;
+  const double hy = R.kxy[a] * wx + R.kyy[a] * wy - Q1;
+  if (R.held[a]) {
+    const double px = R.zx[a], py = R.zy[a];
+    const double gr = R.gx[a] * px + R.gy[a] * py;
+    R.cqx[a] = -py * hx + px * hy - gr * R.cdx[a];
+    R.cqy[a] = 0.0;
+  } else {
+    R.cqx[a] = hx;
+    R.cqy[a] = hy;
   }
 }
 
@@ -912,6 +1008,143 @@ __device__ void apply_prec(bool held, double px, double py, double g0, double g1
   r1 = vy * (p1 / l1) + vx * (p2 / l2);
 }
 
+// Trial point of active a along the coordinate step (d0, d1) from z (held:
+// rotation by the angle d0; free: translation, then the wall projection),
+// with the model's FP32 coordinates of the trial on the mixed path.
+__device__ __forceinline__ void set_trial(RelaxDev& R, const PState& s, int a, double d0,
+                                          double d1) {
+  R.dx[a] = d0;
+  R.dy[a] = d1;
+  double nx, ny;
+  take_step(R.held[a], R.zx[a], R.zy[a], d0, d1, 1.0, nx, ny, R.pin[a], R.sigma);
+  R.tx[a] = nx;
+  R.ty[a] = ny;
+  if (R.a32x) {
+    R.a32x[a] = (float)(nx - s.cx);
+    R.a32y[a] = (float)(ny - s.cy);
+  }
+}
+
+// A coordinate vector in Cartesian form: held charge d0 (-y, x), free (d0, d1).
+__device__ __forceinline__ void to_cart(bool h, double px, double py, double d0, double d1,
+                                        double& wx, double& wy) {
+  wx = h ? -py * d0 : d0;
+  wy = h ? px * d0 : d1;
+}
+
+// Start of a Newton step at z (truncated-Newton polish): preconditioned CG on
+// H_t x = -g_c (g_c the coordinate gradient at z) from x = 0, with the
+// block-Jacobi preconditioner of apply_prec.  The step ends when the
+// residual's inf-norm falls below max(cg_eta |g_c|inf, gtol / 10).
+__device__ void cg_start(RelaxDev& R, PState& s, int p, double gi, WgRed& red) {
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double rz = 0.0, gm = 0.0;
+  for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
+    const bool h = R.held[a];
+    const double px = R.zx[a], py = R.zy[a], g0 = R.gx[a], g1 = R.gy[a];
+    double c0, c1, z0, z1;
+    coord_grad(h, px, py, g0, g1, c0, c1);
+    const double r0 = -c0, r1 = -c1;  // the residual of x = 0
+    apply_prec(h, px, py, g0, g1, R.kxx[a], R.kxy[a], R.kyy[a], r0, r1, z0, z1);
+    R.cgx[a] = 0.0;
+    R.cgy[a] = 0.0;
+    R.crx[a] = r0;
+    R.cry[a] = r1;
+    R.cdx[a] = z0;
+    R.cdy[a] = z1;
+    to_cart(h, px, py, z0, z1, R.cwx[a], R.cwy[a]);
+    rz += r0 * z0 + r1 * z1;
+    gm = fmax(gm, fmax(fabs(c0), fabs(c1)));
+  }
+  block_sum_max(rz, gm, red);
+  s.rz = rz;
+  s.cg_it = 0;
+  s.phase = kPhaseCG;
+  // forcing term: fixed (cg_eta > 0), or adaptive (Eisenstat-Walker's second
+  // choice): 0.9 (g_k / g_{k-1})^2 from the reduced gradients at the starts
+  // of this and the last Newton step, 0.1 for the first, kept above 0.9
+  // eta_{k-1}^2 when that exceeds 0.1 and within [1e-8, 0.1]
+  double eta = R.cg_eta;
+  if (!(eta > 0.0)) {
+    if (s.gnewt > 0.0) {
+      const double q = gi / s.gnewt;
+      eta = 0.9 * q * q;
+      const double prev = 0.9 * s.eta * s.eta;
+      if (prev > 0.1) eta = fmax(eta, prev);
+      eta = fmin(0.1, fmax(eta, 1e-8));
+    } else {
+      eta = 0.1;
+    }
+  }
+  s.eta = eta;
+  s.gnewt = gi;
+  s.cg_target = fmax(eta * gm, 0.1 * R.gtol);
+}
+
+// One CG iteration after k_cg_hvp wrote q = H_t d.  The Newton step ends --
+// and its trial point is set -- when the residual meets the target, at the
+// iteration cap, or when d has non-positive curvature (the step then follows
+// the iterate x, a descent direction, or d itself at the first iteration).
+// Its largest displacement is capped at step0, as for L-BFGS steps.
+__device__ void cg_iteration(RelaxDev& R, PState& s, int p, WgRed& red) {
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double dq = 0.0;
+  for (int a = a0 + threadIdx.x; a < a1; a += kUpd) dq += R.cdx[a] * R.cqx[a] + R.cdy[a] * R.cqy[a];
+  dq = block_sum(dq, red);
+  int end = 0;  // 0: go on, 1: step along the iterate x, 2: along d
+  if (!(dq > 0.0)) {
+    end = s.cg_it == 0 ? 2 : 1;
+  } else {
+    const double al = s.rz / dq;
+    double rz = 0.0, rm = 0.0;
+    for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
+      const double q0 = R.cqx[a], q1 = R.cqy[a];
+      R.cgx[a] += al * R.cdx[a];
+      R.cgy[a] += al * R.cdy[a];
+      const double r0 = R.crx[a] - al * q0, r1 = R.cry[a] - al * q1;
+      R.crx[a] = r0;
+      R.cry[a] = r1;
+      double z0, z1;
+      apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a], r0,
+                 r1, z0, z1);
+      R.cqx[a] = z0;  // q is spent: it holds M^-1 r until d is updated
+      R.cqy[a] = z1;
+      rz += r0 * z0 + r1 * z1;
+      rm = fmax(rm, fmax(fabs(r0), fabs(r1)));
+    }
+    block_sum_max(rz, rm, red);
+    s.cg_it++;
+    if (rm <= s.cg_target || s.cg_it >= R.max_cg || !(rz > 0.0)) {
+      end = 1;
+    } else {
+      const double be = rz / s.rz;
+      s.rz = rz;
+      for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
+        const double d0 = R.cqx[a] + be * R.cdx[a], d1 = R.cqy[a] + be * R.cdy[a];
+        R.cdx[a] = d0;
+        R.cdy[a] = d1;
+        to_cart(R.held[a], R.zx[a], R.zy[a], d0, d1, R.cwx[a], R.cwy[a]);
+      }
+    }
+  }
+  if (end) {
+    double dm = 0.0;
+    for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
+      const double d0 = end == 1 ? R.cgx[a] : R.cdx[a], d1 = end == 1 ? R.cgy[a] : R.cdy[a];
+      dm = fmax(dm, R.held[a] ? fabs(d0) : sqrt(d0 * d0 + d1 * d1));
+    }
+    dm = block_max(dm, red);
+    const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
+    for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
+      const double d0 = end == 1 ? R.cgx[a] : R.cdx[a], d1 = end == 1 ? R.cgy[a] : R.cdy[a];
+      set_trial(R, s, a, d0 * sc, d1 * sc);
+    }
+    s.cg_total += s.cg_it;
+    s.phase = kPhaseStep;
+    s.alpha = 1.0;
+  }
+}
+
 // HT: storage type of the L-BFGS history (FP32 on the mixed path, where it
 // halves the kernel's dominant memory traffic; FP64 on the plain path).  The
 // recursion itself runs in FP64.
@@ -929,7 +1162,13 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   const int p = blockIdx.x, t = threadIdx.x;
   PState s = R.st[p];
   if (s.status != kRunning) return;
+  if (s.phase == kPhaseCG) {
+    cg_iteration(R, s, p, red);
+    if (t == 0) R.st[p] = s;
+    return;
+  }
   s.evals++;
+  const bool was_init = s.init;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int m = R.m;
   double* rho = R.rho + (size_t)p * m;
@@ -1103,6 +1342,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     if (!s.init) {
       s.it++;
       s.total_it++;
+      if (s.newton) s.newton_steps++;
     }
     s.init = 0;
     if (gi <= tol || s.it >= R.max_iter) {
@@ -1113,9 +1353,41 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       }
       return;
     }
+    // truncated-Newton polish: the plain path enters Newton mode below
+    // newton_tol (the mixed path's round check decides there)
+    if (R.polish && !R.fgx && !s.newton_off && gi <= R.newton_tol) s.newton = 1;
+    if (s.newton) {
+      if (R.fgx && !was_init) {
+        // mixed path: one Newton step per expansion of the far field; the
+        // next round re-expands at the new point and tests it exactly
+        if (t == 0) {
+          s.status = kConverged;
+          R.st[p] = s;
+          atomicSub(R.running, 1);
+        }
+        return;
+      }
+      // mixed path, where each Newton step costs a round: a second Newton
+      // step that fails to halve the reduced gradient ends Newton mode for
+      // the patch (e.g. an indefinite Hessian or a changing held set), L-BFGS
+      // from here to the end.  The plain path's steps cost one exact
+      // evaluation each, like an L-BFGS iteration, so it keeps them.
+      if (R.fgx && s.gnewt > 0.0 && gi > 0.5 * s.gnewt && ++s.nfail >= 2) {
+        s.newton = 0;
+        s.newton_off = 1;
+      } else {
+        cg_start(R, s, p, gi, red);
+        if (t == 0) R.st[p] = s;
+        return;
+      }
+    }
   } else {
     s.alpha *= shrink;
-    if (s.alpha >= 1e-10) {
+    if (s.newton && s.alpha < 1e-3) {
+      // the Newton step failed its line search: an L-BFGS direction from z
+      // (the history is kept), Newton again at the next check
+      s.newton = 0;
+    } else if (s.alpha >= 1e-10) {
       for (int a = a0 + t; a < a1; a += kUpd) {
         double nx, ny;
         take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], s.alpha, nx, ny, R.pin[a],
@@ -1129,17 +1401,18 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       }
       if (t == 0) R.st[p] = s;
       return;
-    }
-    if (s.mem == 0) {
-      if (t == 0) {
-        s.status = kLineSearchFail;
-        R.st[p] = s;
-        atomicSub(R.running, 1);
+    } else {
+      if (s.mem == 0) {
+        if (t == 0) {
+          s.status = kLineSearchFail;
+          R.st[p] = s;
+          atomicSub(R.running, 1);
+        }
+        return;
       }
-      return;
+      s.mem = 0;  // restart from steepest descent
+      s.head = 0;
     }
-    s.mem = 0;  // restart from steepest descent
-    s.head = 0;
   }
 
   // new direction: two-loop recursion on the coordinate gradient.  A
@@ -1423,24 +1696,12 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   }
   const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
   s.alpha = 1.0;
-  auto step_to = [&](int a, double d0, double d1) {
-    R.dx[a] = d0;
-    R.dy[a] = d1;
-    double nx, ny;
-    take_step(R.held[a], R.zx[a], R.zy[a], d0, d1, 1.0, nx, ny, R.pin[a], R.sigma);
-    R.tx[a] = nx;
-    R.ty[a] = ny;
-    if (R.a32x) {
-      R.a32x[a] = (float)(nx - s.cx);
-      R.a32y[a] = (float)(ny - s.cy);
-    }
-  };
 #pragma unroll
   for (int j = 0; j < kRegJ; ++j) {
     const int a = a0 + t + j * kUpd;
-    if (a < a1) step_to(a, dxr[j] * sc, dyr[j] * sc);
+    if (a < a1) set_trial(R, s, a, dxr[j] * sc, dyr[j] * sc);
   }
-  for (int a = tail0; a < a1; a += kUpd) step_to(a, R.dx[a] * sc, R.dy[a] * sc);
+  for (int a = tail0; a < a1; a += kUpd) set_trial(R, s, a, R.dx[a] * sc, R.dy[a] * sc);
   if (t == 0) R.st[p] = s;
 }
 
@@ -1456,6 +1717,7 @@ __global__ void k_restart(RelaxDev R, int keep_mem) {
     s.status = kRunning;
   s.init = 1;
   s.it = 0;
+  s.phase = kPhaseStep;
   if (!keep_mem) {
     s.mem = 0;
     s.head = 0;
@@ -1502,6 +1764,7 @@ __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double f
     if (gi <= tol) s.status = kDone;
     ptol[p] = fmax(0.1 * tol, frac * gi);
     s.use32 = gi > tol32;
+    s.newton = R.polish && !s.use32 && !s.newton_off && gi <= R.newton_tol;
     R.st[p] = s;
   }
 }
@@ -1540,6 +1803,10 @@ __global__ __launch_bounds__(kUpd) void k_finish(RelaxDev R, double tol, int exa
     if (status)
       status[p] = !(gi <= tol) ? (s.status == kLineSearchFail ? 2 : s.status == kNonFinite ? 3 : 1)
                                : (isfinite(E) ? 0 : 3);
+    if (R.pstats) {
+      R.pstats[2 * p] = s.newton_steps;
+      R.pstats[2 * p + 1] = s.cg_total;
+    }
   }
 }
 
@@ -1629,6 +1896,16 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.ptol = cv.take<double>(P);
   D.err = cv.take<int32_t>(1);
   D.running = cv.take<int32_t>(1);
+  D.cgx = cv.take<double>(nt);
+  D.cgy = cv.take<double>(nt);
+  D.crx = cv.take<double>(nt);
+  D.cry = cv.take<double>(nt);
+  D.cdx = cv.take<double>(nt);
+  D.cdy = cv.take<double>(nt);
+  D.cqx = cv.take<double>(nt);
+  D.cqy = cv.take<double>(nt);
+  D.cwx = cv.take<double>(nt);
+  D.cwy = cv.take<double>(nt);
   R.hcount = cv.take<int32_t>(P);
   if (precision == CD_MIXED) {
     D.fgx = cv.take<double>(nt);
@@ -1721,6 +1998,12 @@ struct RoundGraphs {
 
 template <class EvalFn>
 static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn& eval) {
+  if (R.D.polish) {  // CG iterations of patches in a Newton step, then the trial evaluations
+    if (shape)
+      hipLaunchKernelGGL((k_cg_hvp<kMWWide>), dim3(R.D.nblk), dim3(64 * kMWWide), 0, s, R.D);
+    else
+      hipLaunchKernelGGL((k_cg_hvp<kMW>), dim3(R.D.nblk), dim3(64 * kMW), 0, s, R.D);
+  }
   eval(s, shape);
   if (hist32)
     hipLaunchKernelGGL(k_update<float>, dim3(R.P), dim3(kUpd), 0, s, R.D);
@@ -1843,6 +2126,9 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   if (!(o.gtol > 0.0) || o.max_iter < 0 || o.halo_width < 0.0 || o.inner_tol < 0.0 ||
       o.step0 < 0.0 || o.max_outer < 0 || !(o.sigma >= 0.0 && o.sigma <= 1.0))
     return CD_ERR_INVALID_ARG;
+  if (o.polish < CD_POLISH_DEFAULT || o.polish > CD_POLISH_LBFGS || o.max_polish_iter < 0 ||
+      !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0))
+    return CD_ERR_INVALID_ARG;
   const int64_t ntot = patch_ptr[n_patches];
   if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
   const int m = o.lbfgs_m > 0 ? o.lbfgs_m : 8;
@@ -1869,8 +2155,24 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   D.sigma = o.sigma > 0.0 ? o.sigma : 1.0;
   g_trace = getenv("CD_RELAX_TRACE") != nullptr;
   D.eval_all = 0;
+  D.tol = o.gtol;
+  D.gtol = o.gtol;
+  // defaults measured on the 256-patch batch at N = 1e5 (gtol 1e-3): the
+  // plain path gains from Newton steps (each replaces many exact O(n_act N)
+  // evaluations by CG iterations over the patch's own pairs); on the mixed
+  // path a CG iteration costs a pair pass like an L-BFGS iteration, and
+  // L-BFGS, which keeps its curvature pairs across rounds, is as fast
+  const bool plain = o.precision == CD_FP64;
+  D.polish = o.polish == CD_POLISH_NEWTON || (o.polish == CD_POLISH_DEFAULT && plain);
+  D.max_cg = o.max_polish_iter > 0 ? o.max_polish_iter : 500;
+  D.newton_tol = o.newton_tol > 0.0 ? o.newton_tol : (plain ? 3e-2 : 3e-5) / (h * h);
+  D.cg_eta = o.cg_eta > 0.0 ? o.cg_eta : (plain ? 1e-2 : 0.0);  // 0: adaptive forcing
+  D.pstats = o.polish_stats;
   const int max_iter_eff = o.max_iter > 0 ? o.max_iter : 1;
-  const int max_rounds = 4 * max_iter_eff + 64;
+  // a Newton step takes up to max_cg CG rounds and a few line-search rounds;
+  // the plain path may take many Newton steps in one run of rounds
+  const int newton_rounds = D.polish ? (D.max_cg + 64) * (o.precision == CD_FP64 ? 32 : 1) : 0;
+  const int max_rounds = 4 * max_iter_eff + 64 + newton_rounds;
 
   std::vector<int2> blk;
   blk.reserve(R.nblk);

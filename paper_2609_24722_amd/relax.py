@@ -30,7 +30,15 @@ class RelaxOpts(ctypes.Structure):
         ("step0", ctypes.c_double),
         ("sigma", ctypes.c_double),
         ("boundary", ctypes.c_void_p),
+        ("polish", ctypes.c_int32),
+        ("max_polish_iter", ctypes.c_int32),
+        ("newton_tol", ctypes.c_double),
+        ("cg_eta", ctypes.c_double),
+        ("polish_stats", ctypes.c_void_p),
     ]
+
+# polish modes of relax_subdomains
+POLISH_DEFAULT, POLISH_NEWTON, POLISH_LBFGS = 0, 1, 2
 
 
 def _bind(L):
@@ -75,18 +83,21 @@ class RelaxResult:
     dE: torch.Tensor       # [P] E_sub(relaxed) - E_sub(snapshot), exact FP64
     e_sub: torch.Tensor    # [P] exact E_sub at the relaxed positions
     gtan_inf: torch.Tensor  # [P] exact reduced-gradient inf-norm
-    iters: torch.Tensor    # [P, 2] L-BFGS iterations, exact evaluations
+    iters: torch.Tensor    # [P, 2] accepted iterations (L-BFGS and Newton), exact evaluations
     status: torch.Tensor   # [P] 0 converged, 1 cap, 2 line search failed, 3 non-finite
+    polish: torch.Tensor   # [P, 2] accepted Newton steps, CG iterations
 
 
 def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
-                     step0=0.0, sigma=0.0, boundary=None) -> RelaxResult:
+                     step0=0.0, sigma=0.0, boundary=None, polish=POLISH_DEFAULT, max_polish_iter=0,
+                     newton_tol=0.0, cg_eta=0.0) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
     the FP64 path.  boundary (device int32 [n]) and sigma select the
-    border-interior split of Sec. II.B."""
+    border-interior split of Sec. II.B.  polish, max_polish_iter, newton_tol
+    and cg_eta set the truncated-Newton polish (0: the library defaults)."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -103,9 +114,11 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     if boundary is not None and (boundary.dtype != torch.int32 or boundary.numel() != n
                                  or boundary.device != dev):
         raise ops.CoulombError("boundary must be a device int32 tensor of length n")
+    pst = torch.empty((P, 2), dtype=torch.int32, device=dev)
     o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), int(max_outer), float(gtol),
                   float(inner_tol), float(halo_width), float(step0), float(sigma),
-                  boundary.data_ptr() if boundary is not None else None)
+                  boundary.data_ptr() if boundary is not None else None, int(polish),
+                  int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr())
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)
@@ -121,7 +134,7 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
         y_start.data_ptr() if y_start is not None else None, ctypes.byref(o),
         xo.data_ptr(), yo.data_ptr(), dE.data_ptr(), es.data_ptr(), gt.data_ptr(), it.data_ptr(),
         stt.data_ptr(), ws.data_ptr(), nb, ops.stream_ptr(dev)), "relax_subdomains")
-    return RelaxResult(xo, yo, dE, es, gt, it, stt)
+    return RelaxResult(xo, yo, dE, es, gt, it, stt, pst)
 
 
 def commit_patches(x, y, ptr, idx, x_rel, y_rel, order_key):

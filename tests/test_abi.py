@@ -88,7 +88,8 @@ def test_relax_argument_errors_before_any_launch(L):
         _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                     ("max_outer", ctypes.c_int32), ("gtol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                     ("halo_width", ctypes.c_double), ("step0", ctypes.c_double), ("sigma", ctypes.c_double),
-                    ("boundary", ctypes.c_void_p)]
+                    ("boundary", ctypes.c_void_p), ("polish", ctypes.c_int32), ("max_polish_iter", ctypes.c_int32),
+                    ("newton_tol", ctypes.c_double), ("cg_eta", ctypes.c_double), ("polish_stats", ctypes.c_void_p)]
     vp = ctypes.c_void_p
     f = L.relax_subdomains
     f.restype = ctypes.c_int
@@ -109,6 +110,15 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(Opts(3, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0), big) == -1    # bad precision
     assert call(Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0, 1.5), big) == -1   # interior wall beyond the disk
     assert call(Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0, -0.1), big) == -1  # negative interior wall
+    def polished(**kw):
+        q = Opts(1, 100, 8, 0, 1e-3, 0.0, 0.0, 0.0)
+        for k, v in kw.items():
+            setattr(q, k, v)
+        return q
+    assert call(polished(polish=3), big) == -1                          # unknown polish mode
+    assert call(polished(max_polish_iter=-1), big) == -1                # negative CG cap
+    assert call(polished(newton_tol=-1.0), big) == -1                   # negative switch
+    assert call(polished(cg_eta=1.0), big) == -1                        # CG target not below 1
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0
