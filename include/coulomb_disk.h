@@ -61,7 +61,8 @@ enum {
   CD_OP_LANCZOS = 6,
   CD_OP_DEFECT = 7,
   CD_OP_ZONES = 8,
-  CD_OP_VORONOI = 9
+  CD_OP_VORONOI = 9,
+  CD_OP_BORDER = 10
 };
 
 /* Per-charge flags written by coulomb_validate. */
@@ -212,6 +213,14 @@ typedef struct {
                                 halve the gradient returns the patch to L-BFGS */
   int32_t* polish_stats;     /* device int32 [2P] or NULL: accepted Newton steps and CG
                                 iterations per patch */
+  double trust_radius;       /* CD_MIXED, in units of h (0 = half the halo width): a round
+                                ends for a patch once one of its actives is farther than
+                                this from the expansion point (the far field is a
+                                quadratic, blind to charges beyond the halo that an
+                                active could reach), and the next round re-expands where
+                                the patch stands; the halos are rebuilt about the current
+                                actives once one has drifted a quarter of the halo width
+                                from where its halo was built */
 } cd_relax_opts;
 
 enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
@@ -337,6 +346,19 @@ int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_
  * synchronise. */
 int border_project(double* x, double* y, int64_t n, const int32_t* flags, double sigma,
                    void* stream);
+
+/* Start of the split before a cycle (a step the paper leaves open; moving
+ * the boundary charges of an unrelaxed configuration along their rays, as
+ * border_project does, lands charges of adjacent rings almost on top of each
+ * other): the charges with flags[i] != 0, ordered by theta = atan2(y, x)
+ * (ties to the lower index), go onto the unit circle at angle theta_0 +
+ * 2 pi k / nb -- k their rank, nb their number, theta_0 the angle of the
+ * first -- as x = cos, y = sin, in place on x, y (device [n]); the others are
+ * unchanged.  flags: device int32 [n].  One workgroup, O(nb^2) comparisons.
+ * ws: coulomb_workspace_bytes(CD_OP_BORDER, n, 0, 0, 0) bytes.  Does not
+ * synchronise. */
+int border_spread(double* x, double* y, int64_t n, const int32_t* flags, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* Structure analysis (Sec. III): Voronoi coordination and psi_6.
  * z[n] (device int32): the number of Voronoi (Delaunay) neighbours of each

@@ -14,6 +14,10 @@ imports the GPU library.
 * ``border_project`` -- the feasible point nearest along the ray: boundary
   charges onto the unit circle (x / r), others beyond sigma onto radius sigma
   (x * (sigma / r)).
+* ``border_spread``  -- the start of the split used before a cycle (a step
+  the paper leaves open): the boundary charges onto the unit circle, evenly
+  spaced in angle in their angular order, so that charges of adjacent rings
+  on one ray do not land on top of each other.
 
 The relaxation under this constraint is ``relax(..., pin=..., sigma=...)`` of
 this package (oracle.c: boundary charges pinned to the unit circle, the others
@@ -68,4 +72,25 @@ def border_project(x, y, flags, sigma: float):
     f = sigma / r[out]
     x[out] = x[out] * f
     y[out] = y[out] * f
+    return x, y
+
+
+def border_spread(x, y, flags):
+    """Copies of (x, y) with the flagged charges moved onto the unit circle:
+    ordered by theta = atan2(y, x) (ties to the lower index), the k-th of the
+    nb flagged charges goes to angle theta_0 + 2 pi k / nb, theta_0 the angle
+    of the first.  Unflagged charges are unchanged."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    y = np.array(y, dtype=np.float64, copy=True)
+    idx = np.flatnonzero(np.asarray(flags) != 0)
+    nb = idx.size
+    if nb == 0:
+        return x, y
+    th = np.arctan2(y[idx], x[idx])
+    order = idx[np.lexsort((idx, th))]  # by angle, then index
+    th0 = float(np.arctan2(y[order[0]], x[order[0]]))
+    for k, i in enumerate(order):
+        phi = th0 + 2.0 * math.pi * k / nb
+        x[i] = math.cos(phi)
+        y[i] = math.sin(phi)
     return x, y

@@ -27,6 +27,9 @@ def _lib():
         L.border_project.restype = ctypes.c_int
         L.border_project.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_void_p]
+        L.border_spread.restype = ctypes.c_int
+        L.border_spread.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L._border_bound = True
     return L
 
@@ -66,3 +69,15 @@ def border_project(x, y, flags, sigma: float) -> None:
     ops.check(_lib().border_project(x.data_ptr(), y.data_ptr(), x.numel(),
                                     flags.data_ptr() if flags is not None else None, float(sigma),
                                     ops.stream_ptr(dev)), "border_project")
+
+
+def border_spread(x, y, flags) -> None:
+    """In place: the flagged charges onto the unit circle, evenly spaced in
+    angle in their angular order (the split's start before a cycle)."""
+    dev = ops._chk(x, y)
+    if flags.dtype != torch.int32 or flags.numel() != x.numel() or flags.device != dev:
+        raise ops.CoulombError("flags must be a device int32 tensor of length n")
+    n = x.numel()
+    ws, nb = ops.workspace(ops.OP_BORDER, n, ops.FP64, dev)
+    ops.check(_lib().border_spread(x.data_ptr(), y.data_ptr(), n, flags.data_ptr(), ws.data_ptr(), nb,
+                                   ops.stream_ptr(dev)), "border_spread")

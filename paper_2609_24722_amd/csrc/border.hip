@@ -113,6 +113,75 @@ __global__ void k_border_project(double* __restrict__ x, double* __restrict__ y,
 }
 #pragma clang fp contract(on)
 
+// Spread of the boundary charges, the split's start before a cycle (a step
+// the paper leaves open; projecting the boundary charges of an unrelaxed
+// configuration along their rays lands charges of adjacent rings almost on
+// top of each other): the flagged charges, ordered by theta = atan2(y, x)
+// with ties to the lower index, go onto the unit circle at theta_0 +
+// 2 pi k / nb (k their rank, theta_0 the angle of the first).  One
+// workgroup: the flagged charges are listed in index order with their angles
+// (contiguous chunks per thread and a scan), then each counts the listed
+// charges before it in that order -- O(nb^2) comparisons, nb the boundary
+// population of Eq. 4 (6099 at N = 1e5).  Scratch: list, rank int32 [n],
+// theta double [n].
+#pragma clang fp contract(off)
+__global__ __launch_bounds__(kBT) void k_border_spread(double* __restrict__ x,
+                                                       double* __restrict__ y, int n,
+                                                       const int32_t* __restrict__ flags,
+                                                       int32_t* __restrict__ list,
+                                                       int32_t* __restrict__ rank,
+                                                       double* __restrict__ theta) {
+  __shared__ uint32_t cnt[kBT];
+  __shared__ double s_th0;
+  const int t = threadIdx.x;
+  const int chunk = (n + kBT - 1) / kBT;
+  const int j0 = min(n, t * chunk), j1 = min(n, j0 + chunk);
+  uint32_t c = 0;
+  for (int j = j0; j < j1; ++j) c += flags[j] != 0;
+  cnt[t] = c;
+  __syncthreads();
+  for (int off = 1; off < kBT; off <<= 1) {
+    const uint32_t b = t >= off ? cnt[t - off] : 0u;
+    __syncthreads();
+    cnt[t] += b;
+    __syncthreads();
+  }
+  uint32_t pos = cnt[t] - c;
+  for (int j = j0; j < j1; ++j) {
+    if (flags[j]) {
+      list[pos] = j;
+      theta[pos] = atan2(y[j], x[j]);
+      ++pos;
+    }
+  }
+  const int nb = (int)cnt[kBT - 1];
+  __syncthreads();  // the list and the angles are complete (workgroup scope)
+  for (int k = t; k < nb; k += kBT) {
+    const double th = theta[k];
+    int r = 0;
+    for (int q = 0; q < nb; ++q) {
+      const double tq = theta[q];
+      r += (tq < th) || (tq == th && q < k);
+    }
+    rank[k] = r;
+    if (r == 0) s_th0 = th;
+  }
+  __syncthreads();
+  const double th0 = s_th0;
+  for (int k = t; k < nb; k += kBT) {
+    const double phi = th0 + ((2.0 * 3.141592653589793) * (double)rank[k]) / (double)nb;
+    const int j = list[k];
+    x[j] = cos(phi);
+    y[j] = sin(phi);
+  }
+}
+#pragma clang fp contract(on)
+
+size_t border_workspace_bytes(int64_t n) {
+  if (n < 1 || n > (1 << 26)) return 0;
+  return (size_t)n * 16 + 1024;
+}
+
 }  // namespace cd
 
 using namespace cd;
@@ -139,6 +208,20 @@ int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_
   if (!x || !y || !flags || n < 1 || n > (1 << 26) || nb < 0 || nb > n) return CD_ERR_INVALID_ARG;
   hipLaunchKernelGGL(k_border_select, dim3(1), dim3(kBT), 0, (hipStream_t)stream, x, y, (int)n,
                      (int)nb, flags);
+  return hip_status(hipGetLastError());
+}
+
+int border_spread(double* x, double* y, int64_t n, const int32_t* flags, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!x || !y || !flags || n < 1 || n > (1 << 26)) return CD_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < border_workspace_bytes(n)) return CD_ERR_WORKSPACE;
+  Carve cv;
+  cv.base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  int32_t* list = cv.take<int32_t>(n);
+  int32_t* rank = cv.take<int32_t>(n);
+  double* theta = cv.take<double>(n);
+  hipLaunchKernelGGL(k_border_spread, dim3(1), dim3(kBT), 0, (hipStream_t)stream, x, y, (int)n,
+                     flags, list, rank, theta);
   return hip_status(hipGetLastError());
 }
 

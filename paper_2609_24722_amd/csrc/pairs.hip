@@ -1249,6 +1249,7 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 size_t lanczos_workspace_bytes(int64_t n, int k);
 size_t zones_workspace_bytes(int op, int64_t n, int32_t n_zones);
 size_t structure_workspace_bytes(int64_t n);
+size_t border_workspace_bytes(int64_t n);
 
 }  // namespace cd
 
@@ -1276,6 +1277,7 @@ size_t coulomb_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t tot
     if (n < 1 || n > (1 << 26)) return 0;
     return cd::structure_workspace_bytes(n);
   }
+  if (op == CD_OP_BORDER) return cd::border_workspace_bytes(n);
   if (op == CD_OP_DEFECT || op == CD_OP_ZONES) {
     if (n < 1 || n > (1 << 26) || (op == CD_OP_ZONES && n_patches < 1)) return 0;
     return cd::zones_workspace_bytes(op, n, n_patches);

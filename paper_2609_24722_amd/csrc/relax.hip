@@ -209,7 +209,7 @@ struct RelaxDev {
   float *h32x, *h32y;      // halo relative to the patch centre (FP32)
   double *h64x, *h64y;     // halo positions, packed (FP64)
   PState* st;              // [P]
-  int32_t* running;        // [1] number of patches still running
+  int32_t* running;        // [2] patches still running; [1] nonzero: a patch asks for a new halo
   // options
   double tol, step0, c1, noise_rel;
   int max_iter, eval_all;
@@ -225,6 +225,9 @@ struct RelaxDev {
   double newton_tol;       // Newton mode below this exact reduced gradient
   double cg_eta;           // CG target: cg_eta * |g|inf of the step's start
   double gtol;             // the call's tolerance on the exact reduced gradient
+  double trust;            // mixed path: model radius about the expansion point
+  double *zhx, *zhy;       // mixed path: active positions when the halo was built
+  double rebuild_d2;       // squared displacement from them that asks for a new halo
   int32_t* pstats;         // [2P] or null: Newton steps and CG iterations per patch
 };
 
@@ -268,6 +271,10 @@ __global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
   }
   R.z0x[a] = R.x[i];
   R.z0y[a] = R.y[i];
+  if (R.zhx) {  // the halo is first built about the snapshot actives
+    R.zhx[a] = R.x[i];
+    R.zhy[a] = R.y[i];
+  }
   double sx = xs ? xs[a] : R.x[i], sy = ys ? ys[a] : R.y[i];
   const int pin = R.bflag ? (R.bflag[i] != 0) : 0;
   R.pin[a] = pin;
@@ -332,11 +339,18 @@ __global__ __launch_bounds__(256) void k_patch_geom(RelaxDev R) {
 
 // Halo of patch p: frozen charges within R_p + w of the patch centre.  Pass 0
 // counts, pass 1 fills (index order, stable) and marks maskAH.
+// geom (nullable): centre and radius [3P] to use instead of the patch state's.
 __global__ __launch_bounds__(1024) void k_halo(RelaxDev R, double w, int fill,
-                                               int32_t* __restrict__ counts) {
+                                               int32_t* __restrict__ counts,
+                                               const double* __restrict__ geom) {
   __shared__ uint32_t cnt[1024];
   const int p = blockIdx.x, t = threadIdx.x;
-  const PState s = R.st[p];
+  PState s = R.st[p];
+  if (geom) {
+    s.cx = geom[3 * p];
+    s.cy = geom[3 * p + 1];
+    s.R = geom[3 * p + 2];
+  }
   const double lim = (s.R + w) * (s.R + w);
   const int chunk = (R.n + blockDim.x - 1) / blockDim.x;
   const int j0 = min(R.n, t * chunk), j1 = min(R.n, j0 + chunk);
@@ -368,6 +382,67 @@ __global__ __launch_bounds__(1024) void k_halo(RelaxDev R, double w, int fill,
                (unsigned long long)(1ull << (j & 63)));
     }
   }
+}
+
+// Halo rebuild (mixed path), when a patch's actives have drifted from where
+// its halo was built: the box centre and radius of the current actives of
+// every patch, into geom [3P] (the same rule as k_patch_geom on the
+// snapshot); then k_geom_commit makes them the patch's and records the
+// positions the new halo is built about.
+__global__ __launch_bounds__(256) void k_patch_recentre(RelaxDev R, double* __restrict__ geom) {
+  __shared__ double red[4][4];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int a = a0 + t; a < a1; a += blockDim.x) {
+    x0 = fmin(x0, R.zx[a]);
+    x1 = fmax(x1, R.zx[a]);
+    y0 = fmin(y0, R.zy[a]);
+    y1 = fmax(y1, R.zy[a]);
+  }
+  x0 = wave_min(x0);
+  x1 = wave_max(x1);
+  y0 = wave_min(y0);
+  y1 = wave_max(y1);
+  if ((t & 63) == 0) {
+    red[t >> 6][0] = x0;
+    red[t >> 6][1] = x1;
+    red[t >> 6][2] = y0;
+    red[t >> 6][3] = y1;
+  }
+  __syncthreads();
+  const double cx = 0.5 * (fmin(fmin(red[0][0], red[1][0]), fmin(red[2][0], red[3][0])) +
+                           fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1])));
+  const double cy = 0.5 * (fmin(fmin(red[0][2], red[1][2]), fmin(red[2][2], red[3][2])) +
+                           fmax(fmax(red[0][3], red[1][3]), fmax(red[2][3], red[3][3])));
+  double rm = 0.0;
+  for (int a = a0 + t; a < a1; a += blockDim.x) {
+    const double dx = R.zx[a] - cx, dy = R.zy[a] - cy;
+    rm = fmax(rm, sqrt(dx * dx + dy * dy));
+  }
+  rm = wave_max(rm);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6][0] = rm;
+  __syncthreads();
+  if (t == 0) {
+    geom[3 * p] = cx;
+    geom[3 * p + 1] = cy;
+    geom[3 * p + 2] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+  }
+}
+
+__global__ void k_geom_commit(RelaxDev R, const double* __restrict__ geom) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < R.P) {
+    R.st[a].cx = geom[3 * a];
+    R.st[a].cy = geom[3 * a + 1];
+    R.st[a].R = geom[3 * a + 2];
+  }
+  if (a < R.ntot) {
+    R.zhx[a] = R.zx[a];
+    R.zhy[a] = R.zy[a];
+  }
+  if (a == 0) R.running[1] = 0;
 }
 
 // ------------------------------------------------------ exact FP64 evaluation --
@@ -881,6 +956,26 @@ __device__ void block_sum_max(double& sm, double& mx, WgRed& R) {
   mx = tm;
 }
 
+// two maxima in one pass
+__device__ void block_max2(double& a, double& b, WgRed& R) {
+  a = wave_max_rows(a);
+  b = wave_max_rows(b);
+  double* r = R.next();
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    r[3 * w] = a;
+    r[3 * w + 1] = b;
+  }
+  __syncthreads();
+  double ta = r[0], tb = r[1];
+  for (int q = 1; q < kUpdWaves; ++q) {
+    ta = fmax(ta, r[3 * q]);
+    tb = fmax(tb, r[3 * q + 1]);
+  }
+  a = ta;
+  b = tb;
+}
+
 // Many sums at once.  rows_sum: each 16-lane row adds every one of the N
 // values by DPP, the row's first lane stores the row sums, then a barrier.
 // rows_total: the total of value q from its kRows row sums, in a fixed order
@@ -1265,9 +1360,13 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     // move to the trial, update the held set
     if (t == 0) s_flag = 0;
     __syncthreads();
-    double gm = 0.0;
+    double gm = 0.0, dz = 0.0;  // reduced gradient; mixed path: displacement from the expansion point
     for (int a = a0 + t; a < a1; a += kUpd) {
       const double px = R.tx[a], py = R.ty[a], g0 = R.hgx[a], g1 = R.hgy[a];
+      if (R.zrx) {
+        const double ex = px - R.zrx[a], ey = py - R.zry[a];
+        dz = fmax(dz, ex * ex + ey * ey);
+      }
       R.zx[a] = px;
       R.zy[a] = py;
       R.gx[a] = g0;
@@ -1305,7 +1404,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       }
       gm = fmax(gm, reduced_inf(px, py, g0, g1, pin, R.sigma));
     }
-    const double gi = block_max(gm, red);
+    block_max2(gm, dz, red);
+    const double gi = gm;
     __syncthreads();
     if (s_flag && s.mem > 0) {
       // entries were converted: every rho again, eight pairs per pass over the
@@ -1345,9 +1445,14 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       if (s.newton) s.newton_steps++;
     }
     s.init = 0;
-    if (gi <= tol || s.it >= R.max_iter) {
+    // mixed path: the model is trusted within trust of its expansion point
+    // (beyond the halo the exterior is a quadratic, blind to charges an
+    // active could run into); a patch that leaves that radius ends the round
+    // and is re-expanded exactly where it stands
+    const bool left = R.zrx && dz > R.trust * R.trust;
+    if (gi <= tol || s.it >= R.max_iter || left) {
       if (t == 0) {
-        s.status = gi <= tol ? kConverged : kIterCap;
+        s.status = (gi <= tol || left) ? kConverged : kIterCap;
         R.st[p] = s;
         atomicSub(R.running, 1);
       }
@@ -1754,14 +1859,19 @@ __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double f
   PState s = R.st[p];
   if (s.status == kNonFinite || s.status == kDone) return;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
-  double gm = 0.0;
-  for (int a = a0 + t; a < a1; a += kUpd)
+  double gm = 0.0, dh = 0.0;  // reduced gradient; squared drift since the halo was built
+  for (int a = a0 + t; a < a1; a += kUpd) {
     gm = fmax(gm, reduced_inf(R.zx[a], R.zy[a], R.hgx[a], R.hgy[a], R.pin[a], R.sigma));
-  const double gi = block_max(gm, red);
+    const double ex = R.zx[a] - R.zhx[a], ey = R.zy[a] - R.zhy[a];
+    dh = fmax(dh, ex * ex + ey * ey);
+  }
+  block_max2(gm, dh, red);
+  const double gi = gm;
   if (t == 0) {
     s.exact_evals++;
     s.gi = gi;
     if (gi <= tol) s.status = kDone;
+    if (s.status != kDone && dh > R.rebuild_d2) atomicOr(&R.running[1], 1);
     ptol[p] = fmax(0.1 * tol, frac * gi);
     s.use32 = gi > tol32;
     s.newton = R.polish && !s.use32 && !s.newton_off && gi <= R.newton_tol;
@@ -1828,6 +1938,7 @@ struct RPlan {
   RelaxDev D;
   int32_t* hcount;  // [P]
   int32_t* blk_host_dummy;
+  double* geom;      // [3P] mixed path: proposed patch centre and radius of a halo rebuild
 };
 
 static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char* base, RPlan& R) {
@@ -1895,7 +2006,7 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.ptr_w = cv.take<int32_t>(P + 1);
   D.ptol = cv.take<double>(P);
   D.err = cv.take<int32_t>(1);
-  D.running = cv.take<int32_t>(1);
+  D.running = cv.take<int32_t>(2);
   D.cgx = cv.take<double>(nt);
   D.cgy = cv.take<double>(nt);
   D.crx = cv.take<double>(nt);
@@ -1923,7 +2034,12 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
     D.h32y = cv.take<float>(R.hcap);
     D.h64x = cv.take<double>(R.hcap);
     D.h64y = cv.take<double>(R.hcap);
+    D.zhx = cv.take<double>(nt);
+    D.zhy = cv.take<double>(nt);
+    R.geom = cv.take<double>(3 * (size_t)P);
   } else {
+    D.zhx = D.zhy = nullptr;
+    R.geom = nullptr;
     D.fgx = D.fgy = D.fhxx = D.fhxy = D.fhyy = D.zrx = D.zry = nullptr;
     D.hptr = D.hidx = nullptr;
     D.a32x = D.a32y = D.h32x = D.h32y = nullptr;
@@ -2127,7 +2243,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       o.step0 < 0.0 || o.max_outer < 0 || !(o.sigma >= 0.0 && o.sigma <= 1.0))
     return CD_ERR_INVALID_ARG;
   if (o.polish < CD_POLISH_DEFAULT || o.polish > CD_POLISH_LBFGS || o.max_polish_iter < 0 ||
-      !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0))
+      !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0) || !(o.trust_radius >= 0.0))
     return CD_ERR_INVALID_ARG;
   const int64_t ntot = patch_ptr[n_patches];
   if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
@@ -2172,7 +2288,10 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   // a Newton step takes up to max_cg CG rounds and a few line-search rounds;
   // the plain path may take many Newton steps in one run of rounds
   const int newton_rounds = D.polish ? (D.max_cg + 64) * (o.precision == CD_FP64 ? 32 : 1) : 0;
-  const int max_rounds = 4 * max_iter_eff + 64 + newton_rounds;
+  // a whole number of graph replays, so that replayed and one-by-one rounds
+  // stop at the same round
+  const int max_rounds =
+      (4 * max_iter_eff + 64 + newton_rounds + kGraphRounds - 1) / kGraphRounds * kGraphRounds;
 
   std::vector<int2> blk;
   blk.reserve(R.nblk);
@@ -2221,23 +2340,50 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       return rc;
   } else {
     const double w = (o.halo_width > 0.0 ? o.halo_width : 4.0) * h;
-    hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 0, R.hcount);
+    // the model is trusted within trust of its expansion point, and the halo
+    // is rebuilt about the current actives once one has drifted a quarter of
+    // the halo width from where it was built: within a round an active then
+    // stays more than a quarter of the width from every frozen charge the
+    // model does not hold explicitly
+    D.trust = (o.trust_radius > 0.0 ? o.trust_radius * h : 0.5 * w);
+    D.rebuild_d2 = 0.0625 * w * w;
     std::vector<int32_t> hc(n_patches), hp(n_patches + 1);
-    if ((rc = hip_status(hipMemcpyAsync(hc.data(), R.hcount, sizeof(int32_t) * n_patches,
-                                        hipMemcpyDeviceToHost, st))))
-      return rc;
-    if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
-    hp[0] = 0;
-    for (int p = 0; p < n_patches; ++p) hp[p + 1] = hp[p] + hc[p];
-    if (hp[n_patches] > R.hcap) return CD_ERR_WORKSPACE;
-    if ((rc = hip_status(hipMemcpyAsync(D.hptr, hp.data(), sizeof(int32_t) * (n_patches + 1),
-                                        hipMemcpyHostToDevice, st))))
-      return rc;
-    hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 1, R.hcount);
+    // halo lists about geom (null: the patch state's centre and radius);
+    // with geom, a halo that would not fit leaves the current one in place
+    auto build_halo = [&](const double* geom, bool& built) -> int {
+      built = false;
+      hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 0, R.hcount, geom);
+      int e = hip_status(hipMemcpyAsync(hc.data(), R.hcount, sizeof(int32_t) * n_patches,
+                                        hipMemcpyDeviceToHost, st));
+      if (!e) e = hip_status(hipStreamSynchronize(st));
+      if (e) return e;
+      hp[0] = 0;
+      for (int p = 0; p < n_patches; ++p) hp[p + 1] = hp[p] + hc[p];
+      if (hp[n_patches] > R.hcap) return geom ? CD_OK : CD_ERR_WORKSPACE;
+      if (geom) {
+        hipLaunchKernelGGL(k_geom_commit, dim3((std::max(n_patches, (int)ntot) + 255) / 256),
+                           dim3(256), 0, st, D, geom);
+        if ((e = hip_status(hipMemcpyAsync(D.maskAH, D.maskA,
+                                           sizeof(uint64_t) * n_patches * R.nbN,
+                                           hipMemcpyDeviceToDevice, st))))
+          return e;
+      }
+      if ((e = hip_status(hipMemcpyAsync(D.hptr, hp.data(), sizeof(int32_t) * (n_patches + 1),
+                                         hipMemcpyHostToDevice, st))))
+        return e;
+      hipLaunchKernelGGL(k_halo, dim3(n_patches), dim3(1024), 0, st, D, w, 1, R.hcount, geom);
+      const int hb = (hp[n_patches] + 255) / 256;
+      hipLaunchKernelGGL(k_model_prep, dim3(tb > hb ? tb : hb), dim3(256), 0, st, D, 1);
+      built = true;
+      return hip_status(hipGetLastError());
+    };
+    if ((rc = hip_status(hipMemsetAsync(D.running + 1, 0, sizeof(int32_t), st)))) return rc;
+    bool built = false;
+    if ((rc = build_halo(nullptr, built))) return rc;
+    int rebuilds = 0;
+    bool rebuild = false;
     RelaxDev Df = D;
     Df.eval_all = 1;
-    const int hb = (hp[n_patches] + 255) / 256;
-    hipLaunchKernelGGL(k_model_prep, dim3(tb > hb ? tb : hb), dim3(256), 0, st, D, 1);
     // 16-wave model blocks when the running patches hold fewer than 512
     // blocks (estimated from the running count)
     auto wide_shape = [&]() {
@@ -2269,6 +2415,13 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     const int outer_max = o.max_outer > 0 ? o.max_outer : 40;
     const bool trace = g_trace;
     for (int outer = 0; outer < outer_max; ++outer) {
+      if (rebuild) {  // a patch drifted from its halo: rebuild every patch's about its actives
+        hipLaunchKernelGGL(k_patch_recentre, dim3(n_patches), dim3(256), 0, st, D, R.geom);
+        if ((rc = build_halo(R.geom, built))) return rc;
+        rebuilds += built;
+        if (!built && (rc = hip_status(hipMemsetAsync(D.running + 1, 0, sizeof(int32_t), st))))
+          return rc;
+      }
       hipLaunchKernelGGL(k_copy_z_to_t, dim3(tb), dim3(256), 0, st, D);
       hipLaunchKernelGGL(k_exact<kFar>, eg, eb, 0, st, Df);
       hipLaunchKernelGGL(k_exact_sum, dim3(tb64), dim3(64 * kESW), 0, st, Df, (int)kFar);
@@ -2277,11 +2430,13 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                          ptol_ws);
       hipLaunchKernelGGL(k_restart, dim3((n_patches + 255) / 256), dim3(256), 0, st, D, outer > 0);
       hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
-      int32_t hr = 0;
-      if ((rc = hip_status(hipMemcpyAsync(&hr, D.running, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                          st))))
+      int32_t hrr[2] = {0, 0};
+      if ((rc = hip_status(hipMemcpyAsync(hrr, D.running, 2 * sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, st))))
         return rc;
       if ((rc = hip_status(hipStreamSynchronize(st)))) return rc;
+      const int32_t hr = hrr[0];
+      rebuild = hrr[1] != 0;
       R.running = hr;
       if (trace) {
         std::vector<PState> hs(n_patches);
@@ -2297,8 +2452,9 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
         }
         fprintf(stderr,
                 "[relax] round %d: running %d (fp32 %d) done %d, exact gi max %.3e, iterations so "
-                "far %ld, lock-step rounds last stage %d\n",
-                outer, hr, n32, nd, gmax, its, g_last_rounds);
+                "far %ld, lock-step rounds last stage %d, halo rebuilds %d%s\n",
+                outer, hr, n32, nd, gmax, its, g_last_rounds, rebuilds,
+                rebuild ? " (rebuild next)" : "");
       }
       if (hr == 0) break;
       D.ptol = ptol_ws;

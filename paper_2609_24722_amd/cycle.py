@@ -67,7 +67,7 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
                  n_lo: int = 200, n_hi: int = 4000, period: int = 250, gap_h: float = 2.0,
                  seed: int = 1006, precision: int = MIXED, gtol: float = 1e-3, log=None, inspect=None,
                  border_nb: int | None = None, sigma_start: float | None = None, sigma_end: float = 1.0,
-                 lbfgs_m: int = 16):
+                 lbfgs_m: int = 16, border_start: str = "spread", relax_kw: dict | None = None):
     """One defect-targeted cycle of T subdomain optimisations (Sec. II.C).
     x, y: device float64 tensors, updated in place.
 
@@ -88,8 +88,11 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
     * With border_nb, the border-interior split of Sec. II.B: the border_nb
       charges farthest from the centre are pinned to the unit circle, the
       others confined within sigma, which rises linearly over the cycle's
-      batches from sigma_start (default Eq. 5's value) to sigma_end; the
-      configuration is projected onto the split at the start.
+      batches from sigma_start (default Eq. 5's value) to sigma_end; at the
+      start the boundary charges are spread evenly along the circle in
+      their angular order (border_start "spread"; "ray": projected along
+      their rays) and the others projected within sigma.
+    * relax_kw: further options of relax_subdomains.
 
     Returns a summary dict (energies, counts, wall time, per-batch records).
     inspect(b, sel, cx, cy, rz, ptr, idx), if given, sees each batch's zones
@@ -107,6 +110,10 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
     if border_nb is not None:
         s0 = B.sigma0(n) if sigma_start is None else float(sigma_start)
         flags = B.border_split(x, y, int(border_nb))
+        if border_start == "spread":
+            B.border_spread(x, y, flags)
+        elif border_start != "ray":
+            raise ValueError("border_start: 'spread' or 'ray'")
         B.border_project(x, y, flags, s0)
     E0, e = ops.energy(x, y, FP64, local=True)
     draws = torch.tensor(W.zone_draws(T, seed), device=dev)
@@ -142,7 +149,7 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
         if flags is not None:
             sig = s0 + (sigma_end - s0) * (b / max(1, nb - 1))
         res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol, sigma=sig, boundary=flags,
-                                 lbfgs_m=lbfgs_m)
+                                 lbfgs_m=lbfgs_m, **(relax_kw or {}))
         com, dc = R.commit_patches(x, y, ptr, idx, res.x, res.y, res.dE.cpu().numpy())
         tracked += float(dc[com == 1].sum())
         st = np.bincount(res.status.cpu().numpy(), minlength=4)[:4]
@@ -151,7 +158,8 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
         relaxed += int(keep.sum())
         actives += int(ptr[-1])
         rec = {"batch": b, "zones": int(keep.sum()), "actives": int(ptr[-1]), "committed": int(com.sum()),
-               "sum_dE": float(dc[com == 1].sum()), "wall_s": time.perf_counter() - t0}
+               "sum_dE": float(dc[com == 1].sum()), "wall_s": time.perf_counter() - t0,
+               "status": st.tolist(), "sigma": sig}
         recs.append(rec)
         if log is not None:
             log(rec)

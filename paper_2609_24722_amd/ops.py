@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcoulombdisk.so")
 
 (OP_ENERGY, OP_FORCES, OP_HVP, OP_VALIDATE, OP_PATCHES, OP_RELAX, OP_LANCZOS, OP_DEFECT, OP_ZONES,
- OP_VORONOI) = range(10)
+ OP_VORONOI, OP_BORDER) = range(11)
 
 _lib = None
 _ws = {}

@@ -35,6 +35,7 @@ class RelaxOpts(ctypes.Structure):
         ("newton_tol", ctypes.c_double),
         ("cg_eta", ctypes.c_double),
         ("polish_stats", ctypes.c_void_p),
+        ("trust_radius", ctypes.c_double),
     ]
 
 # polish modes of relax_subdomains
@@ -91,13 +92,14 @@ class RelaxResult:
 def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
                      step0=0.0, sigma=0.0, boundary=None, polish=POLISH_DEFAULT, max_polish_iter=0,
-                     newton_tol=0.0, cg_eta=0.0) -> RelaxResult:
+                     newton_tol=0.0, cg_eta=0.0, trust_radius=0.0) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
     the FP64 path.  boundary (device int32 [n]) and sigma select the
     border-interior split of Sec. II.B.  polish, max_polish_iter, newton_tol
-    and cg_eta set the truncated-Newton polish (0: the library defaults)."""
+    and cg_eta set the truncated-Newton polish, trust_radius (units of h) the
+    mixed path's model radius (0: the library defaults)."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -118,7 +120,8 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), int(max_outer), float(gtol),
                   float(inner_tol), float(halo_width), float(step0), float(sigma),
                   boundary.data_ptr() if boundary is not None else None, int(polish),
-                  int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr())
+                  int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr(),
+                  float(trust_radius))
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)

@@ -89,7 +89,8 @@ def test_relax_argument_errors_before_any_launch(L):
                     ("max_outer", ctypes.c_int32), ("gtol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                     ("halo_width", ctypes.c_double), ("step0", ctypes.c_double), ("sigma", ctypes.c_double),
                     ("boundary", ctypes.c_void_p), ("polish", ctypes.c_int32), ("max_polish_iter", ctypes.c_int32),
-                    ("newton_tol", ctypes.c_double), ("cg_eta", ctypes.c_double), ("polish_stats", ctypes.c_void_p)]
+                    ("newton_tol", ctypes.c_double), ("cg_eta", ctypes.c_double), ("polish_stats", ctypes.c_void_p),
+                    ("trust_radius", ctypes.c_double)]
     vp = ctypes.c_void_p
     f = L.relax_subdomains
     f.restype = ctypes.c_int
@@ -119,6 +120,7 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(polished(max_polish_iter=-1), big) == -1                # negative CG cap
     assert call(polished(newton_tol=-1.0), big) == -1                   # negative switch
     assert call(polished(cg_eta=1.0), big) == -1                        # CG target not below 1
+    assert call(polished(trust_radius=-1.0), big) == -1                 # negative trust radius
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0

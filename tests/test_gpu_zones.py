@@ -141,5 +141,5 @@ def test_defect_cycle_small(dev, precision):
     assert abs(out["tracked_energy"] - out["E_end"]) <= 1e-12 * out["E_end"]
     assert abs(out["E_end"] - O.energy(xt.cpu().numpy(), yt.cpu().numpy())) <= 1e-13 * out["E_end"]
     assert out["committed"] >= 48
-    assert out["relax_status"][0] >= 90
+    assert out["relax_status"] == [96, 0, 0, 0]  # every zone converges
     assert (np.hypot(xt.cpu().numpy(), yt.cpu().numpy()) <= 1.0 + 1e-15).all()

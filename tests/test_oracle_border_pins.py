@@ -152,3 +152,40 @@ def test_border_project_definition():
     r0, r1 = np.hypot(x, y), np.hypot(px, py)
     assert np.all(r1 <= 0.7 * (1 + 1e-15)) and np.array_equal(px[r0 <= 0.7], x[r0 <= 0.7])
     assert np.allclose(np.arctan2(py, px), np.arctan2(y, x), atol=1e-15)
+
+
+def test_border_spread_pins():
+    # a regular nb-gon on the circle, listed in shuffled order among interior
+    # charges: spreading returns it unchanged (to rounding); the angular
+    # order of any boundary set is kept and the spacing is exactly 2 pi / nb
+    rng = np.random.default_rng(5)
+    nb = 37
+    phi = 0.3 + 2 * np.pi * np.arange(nb) / nb
+    bx, by = np.cos(phi), np.sin(phi)
+    ix = rng.uniform(-0.5, 0.5, 20)
+    iy = rng.uniform(-0.5, 0.5, 20)
+    perm = rng.permutation(nb + 20)
+    x = np.concatenate([bx, ix])[perm]
+    y = np.concatenate([by, iy])[perm]
+    flags = (perm < nb).astype(np.int32)
+    sx, sy = B.border_spread(x, y, flags)
+    assert np.allclose(sx, x, atol=1e-15, rtol=0) and np.allclose(sy, y, atol=1e-15, rtol=0)
+    assert np.array_equal(sx[flags == 0], x[flags == 0]) and np.array_equal(sy[flags == 0], y[flags == 0])
+    # charges of three rings on common rays (the unrelaxed lattice's outer
+    # rings): after spreading every neighbour distance is the chord 2 sin(pi/nb)
+    rays = np.repeat(np.arange(12) * 2 * np.pi / 12, 3)
+    rad = np.tile([0.97, 0.985, 1.0], 12)
+    x, y = rad * np.cos(rays), rad * np.sin(rays)
+    fl = np.ones(36, dtype=np.int32)
+    sx, sy = B.border_spread(x, y, fl)
+    assert np.allclose(np.hypot(sx, sy), 1.0, atol=1e-15, rtol=0)
+    th = np.sort(np.mod(np.arctan2(sy, sx), 2 * np.pi))
+    gaps = np.diff(np.concatenate([th, [th[0] + 2 * np.pi]]))
+    assert np.allclose(gaps, 2 * np.pi / 36, atol=1e-13, rtol=0)
+    # the order: ties in angle (a ray) go to the lower index first
+    k = np.argsort(np.lexsort((np.arange(36), np.arctan2(y, x))))
+    ang = np.mod(np.arctan2(sy, sx) - np.arctan2(sy[np.argmin(k)], sx[np.argmin(k)]), 2 * np.pi)
+    assert np.array_equal(np.argsort(ang, kind="stable"), np.argsort(k, kind="stable"))
+    # nothing flagged: unchanged
+    sx, sy = B.border_spread(x, y, np.zeros(36, dtype=np.int32))
+    assert np.array_equal(sx, x) and np.array_equal(sy, y)
