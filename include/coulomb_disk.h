@@ -221,7 +221,19 @@ typedef struct {
                                 the patch stands; the halos are rebuilt about the current
                                 actives once one has drifted a quarter of the halo width
                                 from where its halo was built */
+  int32_t coords;            /* CD_COORDS_XY: interior charges move in (x, y) under the
+                                wall rule (held on their wall, moving along it, when
+                                pushed outward); CD_COORDS_TU: the parameterisation of
+                                Sec. II.D -- an interior charge moves in (t, u), r =
+                                sigma sin^2 t, x = r cos u, y = r sin u, with the
+                                gradient of Eqs. 8-9, so r <= sigma holds without a wall
+                                rule.  At r = 0 both derivatives vanish for any force, so
+                                interior charges starting within 1e-3 sigma of the centre
+                                keep (x, y).  Boundary charges move by their angle (Eq. 10)
+                                either way.  No Newton polish in (t, u) (L-BFGS only). */
 } cd_relax_opts;
+
+enum { CD_COORDS_XY = 0, CD_COORDS_TU = 1 };
 
 enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
 

@@ -93,6 +93,11 @@ def lib():
         L.orc_relax_bi.restype = None
         L.orc_relax_bi.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _I32, ctypes.c_double, _D, _D,
                                    ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
+        L.orc_relax_tu.restype = None
+        L.orc_relax_tu.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _I32, ctypes.c_double, _D, _D,
+                                   ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
+        L.orc_tu_grad.restype = None
+        L.orc_tu_grad.argtypes = [ctypes.c_int64, _I32, ctypes.c_double, _D, _D, _D, _D]
         L.orc_relax.restype = None
         L.orc_relax.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64, _I32, _D, _D,
                                 ctypes.POINTER(RelaxOpts), ctypes.POINTER(RelaxStats)]
@@ -361,3 +366,41 @@ def tangent_hessian_dense(x, y, idx=None, xa=None, ya=None):
     Q = np.array(cols).T
     Hr = Q.T @ Ha @ Q + np.diag(wdiag)
     return 0.5 * (Hr + Hr.T), Q
+
+
+def tu_grad(kind, sigma, c, gx, gy):
+    """Gradient in the coordinates of Sec. II.D (kind 0 (x, y), 1 boundary
+    angle, 2 interior (t, u); c interleaved per charge) from the Cartesian
+    gradient, by Eqs. 8-10."""
+    kind, pk = _i(kind)
+    c, pc = _d(c)
+    gx, pgx = _d(gx)
+    gy, pgy = _d(gy)
+    out = np.empty(2 * kind.size)
+    lib().orc_tu_grad(kind.size, pk, float(sigma), pc, pgx, pgy, out.ctypes.data_as(_D))
+    return out
+
+
+def relax_tu(x, y, idx, xa=None, ya=None, pin=None, sigma: float = 1.0, gtol=1e-6, max_iter=20000,
+             lbfgs_m=16, step0=None):
+    """Relaxation in the (t, u) coordinates of Sec. II.D (L-BFGS; see
+    oracle.c).  pin (flags per active) marks boundary charges.  Returns
+    (xa, ya, stats dict)."""
+    x, px = _d(x)
+    y, py = _d(y)
+    idx, pidx = _i(idx)
+    if xa is None:
+        xa = x[idx].copy()
+        ya = y[idx].copy()
+    xa = np.array(xa, dtype=np.float64, copy=True)
+    ya = np.array(ya, dtype=np.float64, copy=True)
+    if pin is None:
+        pin = np.zeros(idx.size, dtype=np.int32)
+    pin, ppin = _i(pin)
+    h = spacing(x.size)
+    o = RelaxOpts(int(max_iter), int(lbfgs_m), float(gtol), 0.0,
+                  float(step0 if step0 is not None else 0.1 * h), 0)
+    st = RelaxStats()
+    lib().orc_relax_tu(x.size, px, py, idx.size, pidx, ppin, float(sigma), xa.ctypes.data_as(_D),
+                       ya.ctypes.data_as(_D), ctypes.byref(o), ctypes.byref(st))
+    return xa, ya, {"iters": st.iters, "status": st.status, "gtan_inf": st.gtan_inf}

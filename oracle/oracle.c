@@ -37,6 +37,10 @@
  *   orc_reduce_grad_bi, orc_relax_bi  the same under the border-interior
  *                    constraint of Sec. II.B: boundary charges pinned to the
  *                    unit circle, the others confined to |r| <= sigma.
+ *   orc_tu_grad, orc_relax_tu  the parameterisation of Sec. II.D: interior
+ *                    charges in (t, u) with r = sigma sin^2 t, the gradient
+ *                    by the chain rule of Eqs. 8-9 (boundary charges: Eq. 10),
+ *                    and a relaxation in these coordinates.
  */
 #include <math.h>
 #include <stdint.h>
@@ -775,4 +779,235 @@ void orc_relax(int64_t n, const double *x, const double *y, int64_t na,
                const int32_t *idx, double *xa, double *ya, const orc_relax_opts *o,
                orc_relax_stats *st) {
   orc_relax_bi(n, x, y, na, idx, NULL, 1.0, xa, ya, o, st);
+}
+
+/* ------------------------------------------------------- (t, u) coordinates -- */
+/* Sec. II.D: an interior charge at (t, u) sits at r (cos u, sin u) with
+ * r = sigma sin^2 t; a boundary charge at (cos u, sin u).  Chain rule:
+ *   Eq. 8:  dE/dt = (dE/dx cos u + dE/dy sin u) sigma sin 2t
+ *   Eq. 9:  dE/du = -dE/dx r sin u + dE/dy r cos u
+ *   Eq. 10: dE/du = -dE/dx sin u + dE/dy cos u   (boundary, r = 1)
+ * kind[a]: 0 Cartesian (x, y), 1 boundary (u), 2 interior (t, u). */
+static void tu_pos(int64_t na, const int32_t *kind, double sigma, const double *c, double *xa,
+                   double *ya) {
+  for (int64_t a = 0; a < na; ++a) {
+    if (kind[a] == 2) {
+      double r = sigma * sin(c[2 * a]) * sin(c[2 * a]);
+      xa[a] = r * cos(c[2 * a + 1]);
+      ya[a] = r * sin(c[2 * a + 1]);
+    } else if (kind[a] == 1) {
+      xa[a] = cos(c[2 * a]);
+      ya[a] = sin(c[2 * a]);
+    } else {
+      xa[a] = c[2 * a];
+      ya[a] = c[2 * a + 1];
+    }
+  }
+}
+
+/* Gradient in the coordinates c from the Cartesian gradient (gx, gy). */
+void orc_tu_grad(int64_t na, const int32_t *kind, double sigma, const double *c,
+                 const double *gx, const double *gy, double *gc) {
+  for (int64_t a = 0; a < na; ++a) {
+    if (kind[a] == 2) {
+      double t = c[2 * a], u = c[2 * a + 1];
+      double r = sigma * sin(t) * sin(t);
+      gc[2 * a] = (gx[a] * cos(u) + gy[a] * sin(u)) * sigma * sin(2.0 * t);
+      gc[2 * a + 1] = -gx[a] * r * sin(u) + gy[a] * r * cos(u);
+    } else if (kind[a] == 1) {
+      double u = c[2 * a];
+      gc[2 * a] = -gx[a] * sin(u) + gy[a] * cos(u);
+      gc[2 * a + 1] = 0.0;
+    } else {
+      gc[2 * a] = gx[a];
+      gc[2 * a + 1] = gy[a];
+    }
+  }
+}
+
+/* Largest Cartesian displacement of the coordinate step d (to first order). */
+static double tu_step_len(int64_t na, const int32_t *kind, double sigma, const double *c,
+                          const double *d) {
+  double m = 0.0;
+  for (int64_t a = 0; a < na; ++a) {
+    double l;
+    if (kind[a] == 2) {
+      double t = c[2 * a];
+      double lt = sigma * sin(2.0 * t) * d[2 * a], lu = sigma * sin(t) * sin(t) * d[2 * a + 1];
+      l = sqrt(lt * lt + lu * lu);
+    } else if (kind[a] == 1) {
+      l = fabs(d[2 * a]);
+    } else {
+      l = sqrt(d[2 * a] * d[2 * a] + d[2 * a + 1] * d[2 * a + 1]);
+    }
+    if (l > m) m = l;
+  }
+  return m;
+}
+
+/* Relaxation in the coordinates of Sec. II.D: boundary charges (pin[a] != 0)
+ * by their angle, interior charges by (t, u); interior charges starting
+ * within 1e-3 sigma of the centre keep (x, y) (at r = 0 the derivatives of
+ * Eqs. 8-9 vanish for any force) and are projected onto |r| <= sigma after a
+ * step; t starts at most pi/2 - 1e-8 (at t = pi/2, on the wall, dE/dt
+ * vanishes as well, and a charge pushed inward could not leave).  L-BFGS with H0 = gamma I (gamma = s.y / y.y of the newest pair) and
+ * backtracking: Armijo on the exact energy change while that change exceeds
+ * the rounding of E_sub (1e-14 |E_sub|; a boundary charge evaluated at
+ * (cos u, sin u) sits an ulp off the circle, which with its radial force
+ * alone moves E by more than a converged step does), below it a
+ * derivative-only test (the directional derivative at the trial at most 0.9
+ * of the one at the start in magnitude).  Stops when the inf-norm of the
+ * reduced Cartesian gradient (orc_reduce_grad_bi) is below gtol.  On entry
+ * (xa, ya) hold the start, on exit the relaxed positions. */
+void orc_relax_tu(int64_t n, const double *x, const double *y, int64_t na, const int32_t *idx,
+                  const int32_t *pin, double sigma, double *xa, double *ya,
+                  const orc_relax_opts *o, orc_relax_stats *st) {
+  const wall_t wall = {pin, sigma}, *w = &wall;
+  const int64_t m2 = 2 * na;
+  const int M = o->lbfgs_m > 0 ? o->lbfgs_m : 8;
+  int32_t *kind = malloc(sizeof(int32_t) * na);
+  double *c = malloc(sizeof(double) * m2), *cn = malloc(sizeof(double) * m2);
+  double *gc = malloc(sizeof(double) * m2), *gcn = malloc(sizeof(double) * m2);
+  double *d = malloc(sizeof(double) * m2), *q = malloc(sizeof(double) * m2);
+  double *S = malloc(sizeof(double) * m2 * M), *Yv = malloc(sizeof(double) * m2 * M);
+  double *rho = malloc(sizeof(double) * M), *alf = malloc(sizeof(double) * M);
+  double *gx = malloc(sizeof(double) * na), *gy = malloc(sizeof(double) * na);
+  double *nx = malloc(sizeof(double) * na), *ny = malloc(sizeof(double) * na);
+  double *ngx = malloc(sizeof(double) * na), *ngy = malloc(sizeof(double) * na);
+  double *X0 = malloc(sizeof(double) * n), *Y0 = malloc(sizeof(double) * n);
+  int nmem = 0, head = 0;
+  st->iters = 0;
+  st->newton_steps = 0;
+  st->status = 1;
+
+  project(na, xa, ya, w);
+  for (int64_t a = 0; a < na; ++a) {
+    double r = sqrt(xa[a] * xa[a] + ya[a] * ya[a]);
+    if (pin && pin[a]) {
+      kind[a] = 1;
+      c[2 * a] = atan2(ya[a], xa[a]);
+      c[2 * a + 1] = 0.0;
+    } else if (r >= 1e-3 * sigma) {
+      /* at t = pi/2 dE/dt vanishes for any force: start at most pi/2 - 1e-8 */
+      kind[a] = 2;
+      c[2 * a] = fmin(asin(sqrt(fmin(1.0, r / sigma))), 0.5 * M_PI - 1e-8);
+      c[2 * a + 1] = atan2(ya[a], xa[a]);
+    } else {
+      kind[a] = 0;
+      c[2 * a] = xa[a];
+      c[2 * a + 1] = ya[a];
+    }
+  }
+  tu_pos(na, kind, sigma, c, xa, ya);
+  double Ecur = orc_esub(n, x, y, na, idx, xa, ya, gx, gy);
+  orc_tu_grad(na, kind, sigma, c, gx, gy, gc);
+  double gi = orc_reduce_grad_bi(na, xa, ya, gx, gy, pin, sigma, NULL, NULL, NULL);
+
+  for (int it = 0; it < o->max_iter; ++it) {
+    if (gi <= o->gtol) break;
+    st->iters = it + 1;
+    int took = 0;
+    for (int attempt = 0; attempt < 2 && !took; ++attempt) {
+      memcpy(q, gc, sizeof(double) * m2);
+      for (int k = 0; k < nmem; ++k) {
+        int s = (head - 1 - k + M) % M;
+        alf[s] = rho[s] * dot(m2, S + (int64_t)s * m2, q);
+        for (int64_t t = 0; t < m2; ++t) q[t] -= alf[s] * Yv[(int64_t)s * m2 + t];
+      }
+      double gam = 0.0;
+      if (nmem > 0) {
+        int s = (head - 1 + M) % M;
+        double yy = dot(m2, Yv + (int64_t)s * m2, Yv + (int64_t)s * m2);
+        if (rho[s] > 0.0 && yy > 0.0) gam = 1.0 / (rho[s] * yy);
+      }
+      for (int64_t t = 0; t < m2; ++t) q[t] *= gam;
+      for (int k = nmem - 1; k >= 0; --k) {
+        int s = (head - 1 - k + M) % M;
+        double be = rho[s] * dot(m2, Yv + (int64_t)s * m2, q);
+        for (int64_t t = 0; t < m2; ++t) q[t] += (alf[s] - be) * S[(int64_t)s * m2 + t];
+      }
+      for (int64_t t = 0; t < m2; ++t) d[t] = -q[t];
+      if (!(gam > 0.0) || dot(m2, d, gc) >= 0.0) {
+        /* steepest descent scaled to a first step of step0 */
+        double l = tu_step_len(na, kind, sigma, c, gc);
+        for (int64_t t = 0; t < m2; ++t) d[t] = l > 0.0 ? -gc[t] * (o->step0 / l) : 0.0;
+      }
+      double dm = tu_step_len(na, kind, sigma, c, d);
+      if (dm > o->step0)
+        for (int64_t t = 0; t < m2; ++t) d[t] *= o->step0 / dm;
+      memcpy(X0, x, sizeof(double) * n);
+      memcpy(Y0, y, sizeof(double) * n);
+      for (int64_t a = 0; a < na; ++a) {
+        X0[idx[a]] = xa[a];
+        Y0[idx[a]] = ya[a];
+      }
+      double pred0 = dot(m2, gc, d);
+      double al = 1.0;
+      for (int ls = 0; ls < 40 && pred0 < 0.0; ++ls, al *= 0.5) {
+        for (int64_t t = 0; t < m2; ++t) cn[t] = c[t] + al * d[t];
+        tu_pos(na, kind, sigma, cn, nx, ny);
+        for (int64_t a = 0; a < na; ++a)
+          if (kind[a] == 0) {  /* a Cartesian charge stays within sigma */
+            double r = sqrt(nx[a] * nx[a] + ny[a] * ny[a]);
+            if (r > sigma) {
+              nx[a] *= sigma / r;
+              ny[a] *= sigma / r;
+              cn[2 * a] = nx[a];
+              cn[2 * a + 1] = ny[a];
+            }
+          }
+        double dE = orc_esub_delta(n, X0, Y0, na, idx, nx, ny);
+        if (fabs(dE) > 1e-14 * fabs(Ecur)) {
+          if (dE <= 1e-4 * al * pred0) {
+            took = 1;
+            break;
+          }
+        } else {
+          orc_esub(n, x, y, na, idx, nx, ny, ngx, ngy);
+          orc_tu_grad(na, kind, sigma, cn, ngx, ngy, gcn);
+          if (dot(m2, gcn, d) <= 0.9 * fabs(pred0)) {
+            took = 1;
+            break;
+          }
+        }
+      }
+      if (!took) {
+        if (nmem > 0) {
+          nmem = 0;
+          head = 0;
+          continue;
+        }
+        break;
+      }
+      Ecur = orc_esub(n, x, y, na, idx, nx, ny, ngx, ngy);
+      orc_tu_grad(na, kind, sigma, cn, ngx, ngy, gcn);
+      double *sv = S + (int64_t)head * m2, *yv = Yv + (int64_t)head * m2;
+      for (int64_t t = 0; t < m2; ++t) {
+        sv[t] = cn[t] - c[t];
+        yv[t] = gcn[t] - gc[t];
+      }
+      double sy = dot(m2, sv, yv), ss = dot(m2, sv, sv), yy = dot(m2, yv, yv);
+      if (sy > 1e-12 * sqrt(ss * yy)) {
+        rho[head] = 1.0 / sy;
+        head = (head + 1) % M;
+        if (nmem < M) nmem++;
+      }
+      memcpy(c, cn, sizeof(double) * m2);
+      memcpy(gc, gcn, sizeof(double) * m2);
+      memcpy(xa, nx, sizeof(double) * na);
+      memcpy(ya, ny, sizeof(double) * na);
+      memcpy(gx, ngx, sizeof(double) * na);
+      memcpy(gy, ngy, sizeof(double) * na);
+      gi = orc_reduce_grad_bi(na, xa, ya, gx, gy, pin, sigma, NULL, NULL, NULL);
+    }
+    if (!took) {
+      st->status = 2;
+      break;
+    }
+  }
+  if (gi <= o->gtol) st->status = 0;
+  st->gtan_inf = gi;
+  free(kind); free(c); free(cn); free(gc); free(gcn); free(d); free(q); free(S); free(Yv);
+  free(rho); free(alf); free(gx); free(gy); free(nx); free(ny); free(ngx); free(ngy);
+  free(X0); free(Y0);
 }

@@ -167,6 +167,9 @@ struct PState {
   double cg_target;  // CG: the step ends when the residual's inf-norm is below this
   double gnewt;      // reduced gradient at the start of the last Newton step (0: none)
   double eta;        // relative CG target of the last Newton step
+  double gexact;     // mixed path: the exact reduced gradient at the last round's check
+  int force64;       // mixed path: FP64 model pairs from here on (FP32 rounds stalled)
+  int pad2;
 };
 
 struct RelaxDev {
@@ -192,7 +195,8 @@ struct RelaxDev {
   double *dx, *dy;         // search direction (coordinates: held -> angle in dx)
   double *Sx, *Sy, *Yx, *Yy;  // L-BFGS history [m][ntot]
   double* rho;             // [P][m]
-  int32_t* held;           // [ntot]
+  int32_t* held;           // [ntot] optimisation coordinates: 0 (x, y); 1 the polar angle
+                           // on the circle; kHeldTU the (t, u) of Sec. II.D
   int32_t* pin;            // [ntot] 1: boundary charge pinned to the unit circle
   const int32_t* bflag;    // [n] caller's boundary flags (null: none)
   double sigma;            // wall radius of the charges that are not pinned
@@ -229,6 +233,11 @@ struct RelaxDev {
   double *zhx, *zhy;       // mixed path: active positions when the halo was built
   double rebuild_d2;       // squared displacement from them that asks for a new halo
   int32_t* pstats;         // [2P] or null: Newton steps and CG iterations per patch
+  // (t, u) parameterisation of interior charges (Sec. II.D, Eqs. 8-9)
+  int tu;                  // interior charges start in (t, u) (those beyond tu_rmin)
+  double tu_rmin;          // interior charges starting closer to the centre keep (x, y)
+  double *ct, *cu;         // (t, u) at z of the actives in (t, u) coordinates
+  double *tct, *tcu;       // the same at the trial
 };
 
 // ------------------------------------------------------------ setup kernels --
@@ -250,6 +259,28 @@ __device__ __forceinline__ void project_wall(double& px, double& py, int pin, do
       py *= sig / r;
     }
   }
+}
+
+// The (t, u) parameterisation of an interior charge (Sec. II.D): position
+// r (cos u, sin u) with r = sigma sin^2 t, and the gradient in (t, u) by the
+// chain rule of Eqs. 8-9: dE/dt = (g_x cos u + g_y sin u) sigma sin 2t,
+// dE/du = (-g_x sin u + g_y cos u) r.
+constexpr int kHeldTU = 2;
+__device__ __forceinline__ void tu_position(double sig, double t, double u, double& x, double& y) {
+  const double st = sin(t);
+  const double r = sig * (st * st);
+  double su, cu;
+  sincos(u, &su, &cu);
+  x = r * cu;
+  y = r * su;
+}
+__device__ __forceinline__ void tu_grad(double sig, double t, double u, double g0, double g1,
+                                        double& c0, double& c1) {
+  double su, cu, st, ctt;
+  sincos(u, &su, &cu);
+  sincos(t, &st, &ctt);
+  c0 = (g0 * cu + g1 * su) * (sig * (2.0 * st * ctt));
+  c1 = (-g0 * su + g1 * cu) * (sig * (st * st));
 }
 
 __global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
@@ -279,11 +310,29 @@ __global__ void k_setup_actives(RelaxDev R, const double* __restrict__ xs,
   const int pin = R.bflag ? (R.bflag[i] != 0) : 0;
   R.pin[a] = pin;
   project_wall(sx, sy, pin, R.sigma);
+  int kind = 0;
+  if (R.tu && !pin) {
+    // (t, u) of Sec. II.D for an interior charge, r = sigma sin^2 t: at
+    // r = 0 both derivatives of Eqs. 8-9 vanish for any force, so charges
+    // starting within tu_rmin of the centre keep (x, y) (they lie almost
+    // sigma from the wall).  At t = pi/2 (on the wall) dE/dt vanishes too, so
+    // a charge there pushed inward could not leave: t starts at most
+    // pi/2 - 1e-8 (below an ulp of r).  The position is the one (t, u) gives.
+    const double r = sqrt(sx * sx + sy * sy);
+    if (r >= R.tu_rmin) {
+      kind = kHeldTU;
+      const double t = fmin(asin(sqrt(fmin(1.0, r / R.sigma))), 0.5 * 3.141592653589793 - 1e-8);
+      const double u = atan2(sy, sx);
+      R.ct[a] = R.tct[a] = t;
+      R.cu[a] = R.tcu[a] = u;
+      tu_position(R.sigma, t, u, sx, sy);
+    }
+  }
   R.zx[a] = sx;
   R.zy[a] = sy;
   R.tx[a] = sx;
   R.ty[a] = sy;
-  R.held[a] = 0;
+  R.held[a] = kind;
   const uint64_t bit = 1ull << (i & 63);
   atomicOr((unsigned long long*)&R.maskA[(size_t)lo * R.nbN + (i >> 6)], (unsigned long long)bit);
   atomicOr((unsigned long long*)&R.maskAH[(size_t)lo * R.nbN + (i >> 6)], (unsigned long long)bit);
@@ -1053,6 +1102,9 @@ __device__ void take_step(bool h, double px, double py, double d0, double d1, do
   project_wall(nx, ny, pin, sig);
 }
 
+__device__ __forceinline__ void prec2x2(double a, double b, double c, double q0, double q1,
+                                        double& r0, double& r1);
+
 // Preconditioner H0 = inverse of the charge's own Hessian block (its 2x2
 // block for a free charge; d2E/dtheta2 = t.K.t - g.r_hat for a held one),
 // with |eigenvalues| floored at 1e-3 of the largest when the block is not
@@ -1068,6 +1120,13 @@ __device__ void apply_prec(bool held, double px, double py, double g0, double g1
     r1 = 0.0;
     return;
   }
+  prec2x2(a, b, c, q0, q1, r0, r1);
+}
+
+// r = M^-1 q for the symmetric 2x2 block M = [a b; b c], with |eigenvalues|
+// floored at 1e-3 of the largest when M is not positive definite.
+__device__ __forceinline__ void prec2x2(double a, double b, double c, double q0, double q1,
+                                        double& r0, double& r1) {
   const double tr = a + c, det = a * c - b * b;
   if (tr > 0.0 && det > 1e-6 * tr * tr) {
     r0 = (c * q0 - b * q1) / det;
@@ -1103,15 +1162,86 @@ __device__ void apply_prec(bool held, double px, double py, double g0, double g1
   r1 = vy * (p1 / l1) + vx * (p2 / l2);
 }
 
+// The same for an interior charge in (t, u): J^T B J with J = d(x, y)/d(t, u)
+// (columns sigma sin 2t (cos u, sin u) and r (-sin u, cos u)) and B the
+// charge's own Cartesian block.
+__device__ void tu_prec(double sig, double t, double u, double a, double b, double c, double q0,
+                        double q1, double& r0, double& r1) {
+  double su, cu, st, ctt;
+  sincos(u, &su, &cu);
+  sincos(t, &st, &ctt);
+  const double ft = sig * (2.0 * st * ctt), fu = sig * (st * st);
+  const double jtx = ft * cu, jty = ft * su, jux = -fu * su, juy = fu * cu;
+  const double btx = a * jtx + b * jty, bty = b * jtx + c * jty;
+  const double bux = a * jux + b * juy, buy = b * jux + c * juy;
+  prec2x2(jtx * btx + jty * bty, jtx * bux + jty * buy, jux * bux + juy * buy, q0, q1, r0, r1);
+}
+
+// Kind-dispatched pieces of the optimiser for active a (held[a]: 0 (x, y),
+// 1 the angle on its circle, kHeldTU the (t, u) of Sec. II.D): the gradient
+// in optimisation coordinates at z and at the trial, the position after the
+// coordinate step al (d0, d1) from z (a (t, u) charge records its trial
+// (t, u)), the preconditioner at z, and the length of a step's displacement.
+template <bool TU>
+__device__ __forceinline__ void cgrad_z(const RelaxDev& R, int a, double g0, double g1,
+                                        double& c0, double& c1) {
+  const int h = R.held[a];
+  if (TU && h == kHeldTU) tu_grad(R.sigma, R.ct[a], R.cu[a], g0, g1, c0, c1);
+  else coord_grad(h != 0, R.zx[a], R.zy[a], g0, g1, c0, c1);
+}
+template <bool TU>
+__device__ __forceinline__ void cgrad_t(const RelaxDev& R, int a, double g0, double g1,
+                                        double& c0, double& c1) {
+  const int h = R.held[a];
+  if (TU && h == kHeldTU) tu_grad(R.sigma, R.tct[a], R.tcu[a], g0, g1, c0, c1);
+  else coord_grad(h != 0, R.tx[a], R.ty[a], g0, g1, c0, c1);
+}
+template <bool TU>
+__device__ __forceinline__ void step_from_z(RelaxDev& R, int a, double d0, double d1, double al,
+                                            double& nx, double& ny) {
+  const int h = R.held[a];
+  if (TU && h == kHeldTU) {
+    const double t = R.ct[a] + al * d0, u = R.cu[a] + al * d1;
+    R.tct[a] = t;
+    R.tcu[a] = u;
+    tu_position(R.sigma, t, u, nx, ny);
+  } else {
+    take_step(h != 0, R.zx[a], R.zy[a], d0, d1, al, nx, ny, R.pin[a], R.sigma);
+  }
+}
+template <bool TU>
+__device__ __forceinline__ void prec_z(const RelaxDev& R, int a, double q0, double q1, double& r0,
+                                       double& r1) {
+  const int h = R.held[a];
+  if (TU && h == kHeldTU)
+    tu_prec(R.sigma, R.ct[a], R.cu[a], R.kxx[a], R.kxy[a], R.kyy[a], q0, q1, r0, r1);
+  else
+    apply_prec(h != 0, R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a], q0, q1,
+               r0, r1);
+}
+template <bool TU>
+__device__ __forceinline__ double step_len(const RelaxDev& R, int a, double d0, double d1) {
+  const int h = R.held[a];
+  if (TU && h == kHeldTU) {
+    double st, ctt;
+    sincos(R.ct[a], &st, &ctt);
+    const double lt = R.sigma * (2.0 * st * ctt) * d0, lu = R.sigma * (st * st) * d1;
+    return sqrt(lt * lt + lu * lu);
+  }
+  return h ? fabs(d0) : sqrt(d0 * d0 + d1 * d1);
+}
+
 // Trial point of active a along the coordinate step (d0, d1) from z (held:
-// rotation by the angle d0; free: translation, then the wall projection),
-// with the model's FP32 coordinates of the trial on the mixed path.
+// rotation by the angle d0; free: translation, then the wall projection;
+// (t, u): the position the stepped (t, u) gives), with the model's FP32
+// coordinates of the trial on the mixed path.
+template <bool TU>
 __device__ __forceinline__ void set_trial(RelaxDev& R, const PState& s, int a, double d0,
                                           double d1) {
   R.dx[a] = d0;
   R.dy[a] = d1;
   double nx, ny;
-  take_step(R.held[a], R.zx[a], R.zy[a], d0, d1, 1.0, nx, ny, R.pin[a], R.sigma);
+  step_from_z<TU>(R, a, d0, d1, 1.0, nx, ny);
   R.tx[a] = nx;
   R.ty[a] = ny;
   if (R.a32x) {
@@ -1232,7 +1362,7 @@ __device__ void cg_iteration(RelaxDev& R, PState& s, int p, WgRed& red) {
     const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
     for (int a = a0 + threadIdx.x; a < a1; a += kUpd) {
       const double d0 = end == 1 ? R.cgx[a] : R.cdx[a], d1 = end == 1 ? R.cgy[a] : R.cdy[a];
-      set_trial(R, s, a, d0 * sc, d1 * sc);
+      set_trial<false>(R, s, a, d0 * sc, d1 * sc);
     }
     s.cg_total += s.cg_it;
     s.phase = kPhaseStep;
@@ -1243,7 +1373,7 @@ __device__ void cg_iteration(RelaxDev& R, PState& s, int p, WgRed& red) {
 // HT: storage type of the L-BFGS history (FP32 on the mixed path, where it
 // halves the kernel's dominant memory traffic; FP64 on the plain path).  The
 // recursion itself runs in FP64.
-template <class HT>
+template <class HT, bool TU>
 __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   HT* const Sx = reinterpret_cast<HT*>(R.Sx);
   HT* const Sy = reinterpret_cast<HT*>(R.Sy);
@@ -1285,6 +1415,15 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     const double gx = R.gx[a], gy = R.gy[a], hgx = R.hgx[a], hgy = R.hgy[a];
     const double zx = R.zx[a], zy = R.zy[a], tx = R.tx[a], ty = R.ty[a], dx = R.dx[a];
     const double st = s.alpha * dx;
+    if (TU && h == kHeldTU) {  // the step in (t, u) is alpha d
+      double c0, c1, n0, n1;
+      cgrad_z<TU>(R, a, gx, gy, c0, c1);
+      cgrad_t<TU>(R, a, hgx, hgy, n0, n1);
+      const double su = s.alpha * R.dy[a];
+      pr += c0 * st + c1 * su;
+      pt += n0 * st + n1 * su;
+      continue;
+    }
     const double ddx = tx - zx, ddy = ty - zy;
     const double prh = (-gx * zy + gy * zx) * st, pth = (-hgx * ty + hgy * tx) * st;
     const double prf = gx * ddx + gy * ddy, ptf = hgx * ddx + hgy * ddy;
@@ -1326,14 +1465,17 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       double syp = 0.0, ssp = 0.0, yyp = 0.0;
       const int k = s.head;
       for (int a = a0 + t; a < a1; a += kUpd) {
-        const bool h = R.held[a];
+        const int hk = R.held[a];
+        const bool h = hk != 0;
         const double zx = R.zx[a], zy = R.zy[a], tx = R.tx[a], ty = R.ty[a], dx = R.dx[a];
         const double gx = R.gx[a], gy = R.gy[a], hgx = R.hgx[a], hgy = R.hgy[a];
         double c0, c1, n0, n1;
+        // the step in coordinates: the angle step of a held charge, alpha d
+        // in (t, u), the Cartesian displacement of a free charge
         const double s0 = h ? s.alpha * dx : tx - zx;
-        const double s1 = h ? 0.0 : ty - zy;
-        coord_grad(h, zx, zy, gx, gy, c0, c1);
-        coord_grad(h, tx, ty, hgx, hgy, n0, n1);
+        const double s1 = TU && hk == kHeldTU ? s.alpha * R.dy[a] : (h ? 0.0 : ty - zy);
+        cgrad_z<TU>(R, a, gx, gy, c0, c1);
+        cgrad_t<TU>(R, a, hgx, hgy, n0, n1);
         // the pair as stored (rounded to HT), so that rho matches the vectors
         const HT hs0 = (HT)s0, hs1 = (HT)s1, hy0 = (HT)(n0 - c0), hy1 = (HT)(n1 - c1);
         const size_t q = (size_t)k * R.ntot + a;
@@ -1375,8 +1517,13 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       R.kxy[a] = R.hkxy[a];
       R.kyy[a] = R.hkyy[a];
       const int pin = R.pin[a];
-      const int h = held_rule(px, py, g0, g1, pin, R.sigma);
-      if (h != R.held[a]) {
+      const int hk = R.held[a];
+      if (TU && hk == kHeldTU) {  // (t, u) charges keep their coordinates: no wall to hold them
+        R.ct[a] = R.tct[a];
+        R.cu[a] = R.tcu[a];
+      }
+      const int h = TU && hk == kHeldTU ? kHeldTU : held_rule(px, py, g0, g1, pin, R.sigma);
+      if (h != hk) {
         R.held[a] = h;
         if (!s.init) {
           // the charge's history into its new coordinates, keeping the
@@ -1495,8 +1642,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     } else if (s.alpha >= 1e-10) {
       for (int a = a0 + t; a < a1; a += kUpd) {
         double nx, ny;
-        take_step(R.held[a], R.zx[a], R.zy[a], R.dx[a], R.dy[a], s.alpha, nx, ny, R.pin[a],
-                  R.sigma);
+        step_from_z<TU>(R, a, R.dx[a], R.dy[a], s.alpha, nx, ny);
         R.tx[a] = nx;
         R.ty[a] = ny;
         if (R.a32x) {  // the model's FP32 coordinates of the trial
@@ -1534,11 +1680,11 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     for (int j = 0; j < kRegJ; ++j) {
       const int a = a0 + t + j * kUpd;
       qx[j] = qy[j] = 0.0;
-      if (a < a1) coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], qx[j], qy[j]);
+      if (a < a1) cgrad_z<TU>(R, a, R.gx[a], R.gy[a], qx[j], qy[j]);
     }
     for (int a = tail0; a < a1; a += kUpd) {
       double c0, c1;
-      coord_grad(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      cgrad_z<TU>(R, a, R.gx[a], R.gy[a], c0, c1);
       R.dx[a] = c0;
       R.dy[a] = c1;
     }
@@ -1659,16 +1805,14 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       const int a = a0 + t + j * kUpd;
       if (a < a1) {
         double r0, r1;
-        apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
-                   qx[j], qy[j], r0, r1);
+        prec_z<TU>(R, a, qx[j], qy[j], r0, r1);
         qx[j] = r0;
         qy[j] = r1;
       }
     }
     for (int a = tail0; a < a1; a += kUpd) {
       double r0, r1;
-      apply_prec(R.held[a], R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a],
-                 R.dx[a], R.dy[a], r0, r1);
+      prec_z<TU>(R, a, R.dx[a], R.dy[a], r0, r1);
       R.dx[a] = r0;
       R.dy[a] = r1;
     }
@@ -1756,24 +1900,22 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     const int a = a0 + t + j * kUpd;
     if (a < a1) {
       double c0, c1;
-      const bool h = R.held[a];
-      coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+      cgrad_z<TU>(R, a, R.gx[a], R.gy[a], c0, c1);
       const double d0 = -dxr[j], d1 = -dyr[j];
       dxr[j] = d0;
       dyr[j] = d1;
       dg += d0 * c0 + d1 * c1;
-      dm = fmax(dm, h ? fabs(d0) : sqrt(d0 * d0 + d1 * d1));
+      dm = fmax(dm, step_len<TU>(R, a, d0, d1));
     }
   }
   for (int a = tail0; a < a1; a += kUpd) {
     double c0, c1;
-    const bool h = R.held[a];
-    coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
+    cgrad_z<TU>(R, a, R.gx[a], R.gy[a], c0, c1);
     const double d0 = -R.dx[a], d1 = -R.dy[a];
     R.dx[a] = d0;
     R.dy[a] = d1;
     dg += d0 * c0 + d1 * c1;
-    dm = fmax(dm, h ? fabs(d0) : sqrt(d0 * d0 + d1 * d1));
+    dm = fmax(dm, step_len<TU>(R, a, d0, d1));
   }
   block_sum_max(dg, dm, red);
   const bool steep = !(dg < 0.0);
@@ -1781,13 +1923,11 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     dm = 0.0;
     for (int a = a0 + t; a < a1; a += kUpd) {
       double c0, c1, r0, r1;
-      const bool h = R.held[a];
-      coord_grad(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], c0, c1);
-      apply_prec(h, R.zx[a], R.zy[a], R.gx[a], R.gy[a], R.kxx[a], R.kxy[a], R.kyy[a], c0, c1, r0,
-                 r1);
+      cgrad_z<TU>(R, a, R.gx[a], R.gy[a], c0, c1);
+      prec_z<TU>(R, a, c0, c1, r0, r1);
       R.dx[a] = -r0;
       R.dy[a] = -r1;
-      dm = fmax(dm, h ? fabs(r0) : sqrt(r0 * r0 + r1 * r1));
+      dm = fmax(dm, step_len<TU>(R, a, r0, r1));
     }
     dm = block_max(dm, red);
 #pragma unroll
@@ -1804,9 +1944,9 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
 #pragma unroll
   for (int j = 0; j < kRegJ; ++j) {
     const int a = a0 + t + j * kUpd;
-    if (a < a1) set_trial(R, s, a, dxr[j] * sc, dyr[j] * sc);
+    if (a < a1) set_trial<TU>(R, s, a, dxr[j] * sc, dyr[j] * sc);
   }
-  for (int a = tail0; a < a1; a += kUpd) set_trial(R, s, a, R.dx[a] * sc, R.dy[a] * sc);
+  for (int a = tail0; a < a1; a += kUpd) set_trial<TU>(R, s, a, R.dx[a] * sc, R.dy[a] * sc);
   if (t == 0) R.st[p] = s;
 }
 
@@ -1836,6 +1976,8 @@ __global__ void k_copy_z_to_t(RelaxDev R) {
   if (a >= R.ntot) return;
   R.tx[a] = R.zx[a];
   R.ty[a] = R.zy[a];
+  R.tct[a] = R.ct[a];  // the trial's (t, u) with it (used by (t, u) charges only)
+  R.tcu[a] = R.cu[a];
 }
 
 __global__ void k_count_running(RelaxDev R) {
@@ -1868,12 +2010,21 @@ __global__ __launch_bounds__(kUpd) void k_check(RelaxDev R, double tol, double f
   block_max2(gm, dh, red);
   const double gi = gm;
   if (t == 0) {
+    // (t, u) coordinates: a round on the FP32 model that failed to bring the
+    // exact gradient below 0.9 of the last check's has hit the model's
+    // rounding -- a charge pushed against its wall approaches it as
+    // sigma sin^2 t, and its last displacement to the wall (which the exact
+    // test needs within 1e-14) is below FP32 resolution: the patch's model
+    // uses FP64 pairs from here on.  (In (x, y) such a charge is held on the
+    // wall and a stalled round only means a slow one.)
+    if (R.tu && s.use32 && s.exact_evals > 0 && gi > 0.9 * s.gexact) s.force64 = 1;
+    s.gexact = gi;
     s.exact_evals++;
     s.gi = gi;
     if (gi <= tol) s.status = kDone;
     if (s.status != kDone && dh > R.rebuild_d2) atomicOr(&R.running[1], 1);
     ptol[p] = fmax(0.1 * tol, frac * gi);
-    s.use32 = gi > tol32;
+    s.use32 = gi > tol32 && !s.force64;
     s.newton = R.polish && !s.use32 && !s.newton_off && gi <= R.newton_tol;
     R.st[p] = s;
   }
@@ -2017,6 +2168,10 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   D.cqy = cv.take<double>(nt);
   D.cwx = cv.take<double>(nt);
   D.cwy = cv.take<double>(nt);
+  D.ct = cv.take<double>(nt);
+  D.cu = cv.take<double>(nt);
+  D.tct = cv.take<double>(nt);
+  D.tcu = cv.take<double>(nt);
   R.hcount = cv.take<int32_t>(P);
   if (precision == CD_MIXED) {
     D.fgx = cv.take<double>(nt);
@@ -2121,10 +2276,16 @@ static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn
       hipLaunchKernelGGL((k_cg_hvp<kMW>), dim3(R.D.nblk), dim3(64 * kMW), 0, s, R.D);
   }
   eval(s, shape);
-  if (hist32)
-    hipLaunchKernelGGL(k_update<float>, dim3(R.P), dim3(kUpd), 0, s, R.D);
+  // the (t, u) variant only when the call asked for it: the (x, y) kernel
+  // carries none of its branches
+  if (hist32 && R.D.tu)
+    hipLaunchKernelGGL((k_update<float, true>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else if (hist32)
+    hipLaunchKernelGGL((k_update<float, false>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else if (R.D.tu)
+    hipLaunchKernelGGL((k_update<double, true>), dim3(R.P), dim3(kUpd), 0, s, R.D);
   else
-    hipLaunchKernelGGL(k_update<double>, dim3(R.P), dim3(kUpd), 0, s, R.D);
+    hipLaunchKernelGGL((k_update<double, false>), dim3(R.P), dim3(kUpd), 0, s, R.D);
 }
 
 // eval(stream, shape) enqueues one evaluation; shape(): 0 or 1, the
@@ -2243,7 +2404,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       o.step0 < 0.0 || o.max_outer < 0 || !(o.sigma >= 0.0 && o.sigma <= 1.0))
     return CD_ERR_INVALID_ARG;
   if (o.polish < CD_POLISH_DEFAULT || o.polish > CD_POLISH_LBFGS || o.max_polish_iter < 0 ||
-      !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0) || !(o.trust_radius >= 0.0))
+      !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0) || !(o.trust_radius >= 0.0) ||
+      (o.coords != CD_COORDS_XY && o.coords != CD_COORDS_TU))
     return CD_ERR_INVALID_ARG;
   const int64_t ntot = patch_ptr[n_patches];
   if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
@@ -2279,7 +2441,10 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   // path a CG iteration costs a pair pass like an L-BFGS iteration, and
   // L-BFGS, which keeps its curvature pairs across rounds, is as fast
   const bool plain = o.precision == CD_FP64;
-  D.polish = o.polish == CD_POLISH_NEWTON || (o.polish == CD_POLISH_DEFAULT && plain);
+  D.tu = o.coords == CD_COORDS_TU;
+  D.tu_rmin = 1e-3 * D.sigma;
+  // the Newton steps work in (x, y) and angle coordinates: none in (t, u)
+  D.polish = !D.tu && (o.polish == CD_POLISH_NEWTON || (o.polish == CD_POLISH_DEFAULT && plain));
   D.max_cg = o.max_polish_iter > 0 ? o.max_polish_iter : 500;
   D.newton_tol = o.newton_tol > 0.0 ? o.newton_tol : (plain ? 3e-2 : 3e-5) / (h * h);
   D.cg_eta = o.cg_eta > 0.0 ? o.cg_eta : (plain ? 1e-2 : 0.0);  // 0: adaptive forcing

@@ -36,10 +36,13 @@ class RelaxOpts(ctypes.Structure):
         ("cg_eta", ctypes.c_double),
         ("polish_stats", ctypes.c_void_p),
         ("trust_radius", ctypes.c_double),
+        ("coords", ctypes.c_int32),
     ]
 
 # polish modes of relax_subdomains
 POLISH_DEFAULT, POLISH_NEWTON, POLISH_LBFGS = 0, 1, 2
+# coordinates of interior charges: (x, y) under the wall rule, or (t, u) of Sec. II.D
+COORDS_XY, COORDS_TU = 0, 1
 
 
 def _bind(L):
@@ -92,14 +95,15 @@ class RelaxResult:
 def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
                      step0=0.0, sigma=0.0, boundary=None, polish=POLISH_DEFAULT, max_polish_iter=0,
-                     newton_tol=0.0, cg_eta=0.0, trust_radius=0.0) -> RelaxResult:
+                     newton_tol=0.0, cg_eta=0.0, trust_radius=0.0, coords=COORDS_XY) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
     the FP64 path.  boundary (device int32 [n]) and sigma select the
     border-interior split of Sec. II.B.  polish, max_polish_iter, newton_tol
     and cg_eta set the truncated-Newton polish, trust_radius (units of h) the
-    mixed path's model radius (0: the library defaults)."""
+    mixed path's model radius (0: the library defaults); coords COORDS_TU
+    moves interior charges in the (t, u) of Sec. II.D."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -121,7 +125,7 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
                   float(inner_tol), float(halo_width), float(step0), float(sigma),
                   boundary.data_ptr() if boundary is not None else None, int(polish),
                   int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr(),
-                  float(trust_radius))
+                  float(trust_radius), int(coords))
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)
