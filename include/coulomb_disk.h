@@ -267,6 +267,27 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
                      double* gtan_inf, int32_t* iters, int32_t* status, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* Schedule tuning of relax_subdomains (not an operation of the paper; a
+ * performance setting).  Relaxes the given batch once with each candidate
+ * schedule -- the running-block count below which the model evaluation
+ * spreads a 64-active block over 16 waves instead of 8 (0, 256, 512, 1024,
+ * always), lock-step rounds per HIP graph replay (4, 8, 16, 32), and, for a
+ * call that leaves polish at CD_POLISH_DEFAULT, the path's other polish
+ * (Newton on CD_MIXED, L-BFGS on CD_FP64) -- outputs discarded, timed on the
+ * host, and keeps the fastest for later relax_subdomains calls on the
+ * current device with the same precision, coordinates, n and
+ * floor(log2(patch_ptr[P])) (process-wide, thread-safe).  A schedule only
+ * changes the order of work, and with it the rounding (the L-BFGS or Newton
+ * polish choice changes the optimiser: any endpoint still meets the
+ * tolerance).  Arguments as relax_subdomains; choice_out: host int32 [4] =
+ * chosen index, wide-block count, rounds per replay, polish (-1 default,
+ * 1 the other); times_out (nullable): host double [9], seconds per
+ * candidate.  Synchronises the stream. */
+int relax_autotune(const double* x, const double* y, int64_t n, int32_t n_patches,
+                   const int32_t* patch_ptr, const int32_t* active_idx, const double* x_start,
+                   const double* y_start, const cd_relax_opts* opts, void* ws, size_t ws_bytes,
+                   void* stream, int32_t* choice_out, double* times_out);
+
 /* Defect-targeted zones of a subdomain cycle (Sec. II.C).  Options (host
  * struct) of defect_zones. */
 typedef struct {

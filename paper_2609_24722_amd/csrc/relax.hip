@@ -30,9 +30,14 @@
 // an Armijo test.  All patches advance in lock step: each round is one
 // evaluation kernel over every running patch plus one update kernel with a
 // workgroup per patch.
+#include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -2085,6 +2090,12 @@ __global__ __launch_bounds__(kUpd) void k_finish_delta(RelaxDev R, double* __res
 struct RPlan {
   int n, P, nbN, m, ntot, nblk, splits, jb, hcap;
   int running;  // patches running at the last read-back (host copy)
+  // schedule (relax_autotune chooses among these): lock-step rounds per graph
+  // replay (the running count is read back between replays), and the
+  // running-block count below which the model evaluation takes 16 waves per
+  // block instead of 8
+  int graph_rounds = 8;
+  int64_t wide_blocks = 512;
   size_t total;
   RelaxDev D;
   int32_t* hcount;  // [P]
@@ -2226,15 +2237,52 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 // Returns a CD status.
 static int g_last_rounds = 0;
 static bool g_trace = false;  // CD_RELAX_TRACE set: progress lines on stderr
-constexpr int kGraphRounds = 8;  // rounds per graph launch (the running count is read between)
 
-// The rounds of one relax call as HIP graphs: kGraphRounds rounds (model or
+// Relax schedules relax_autotune chooses among (the first is the default):
+// the running-block count below which model blocks take 16 waves, lock-step
+// rounds per graph replay, and the polish of a call that left it at
+// CD_POLISH_DEFAULT (-1: the path's default; kOtherPolish: Newton on the
+// mixed path, L-BFGS on the plain one).  The update kernel's workgroup shape
+// is fixed (1024 threads, four register-held actives each: 512 and 256
+// threads were slower on both the batch of 256 patches and the cycle).
+struct RelaxSched {
+  int64_t wide_blocks;
+  int graph_rounds;
+  int polish;
+};
+constexpr int kOtherPolish = 1;
+constexpr RelaxSched kRelaxScheds[] = {{512, 8, -1},  {0, 8, -1},         {1 << 30, 8, -1},
+                                       {256, 8, -1},  {1024, 8, -1},      {512, 4, -1},
+                                       {512, 16, -1}, {512, 32, -1},      {512, 8, kOtherPolish}};
+constexpr int kNumRelaxScheds = sizeof(kRelaxScheds) / sizeof(kRelaxScheds[0]);
+using RelaxKey = std::tuple<int, int, int, int64_t, int>;  // device, precision, coords, n, log2 total
+static std::mutex g_rtune_mu;
+static std::map<RelaxKey, int> g_rtuned;
+static thread_local int g_force_sched = -1;  // the candidate relax_autotune is timing
+
+static RelaxKey relax_key(int precision, int coords, int64_t n, int64_t ntot) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= ntot) ++lg;
+  return std::make_tuple(dev, precision, coords, n, lg);
+}
+
+static int relax_sched_index(int precision, int coords, int64_t n, int64_t ntot) {
+  if (g_force_sched >= 0) return g_force_sched;
+  std::lock_guard<std::mutex> lk(g_rtune_mu);
+  auto it = g_rtuned.find(relax_key(precision, coords, n, ntot));
+  return it == g_rtuned.end() ? 0 : it->second;
+}
+
+// The rounds of one relax call as HIP graphs: graph_rounds rounds (model or
 // exact evaluation, then the update) are captured once per evaluation shape
 // on a private stream, which follows the caller's stream through events (a
 // caller's default stream cannot be captured), and replayed until no patch
 // runs.  The kernels and their arguments are those of the plain launches, so
 // the results are the same bit for bit.  CD_RELAX_GRAPH=0 selects the plain
-// launches; a graph that cannot be built falls back to them.
+// launches; when a graph cannot be captured or instantiated the rounds go on
+// as plain launches.
 struct RoundGraphs {
   hipStream_t cs = nullptr;
   hipEvent_t ev = nullptr;
@@ -2295,24 +2343,37 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Rou
                       EvalFn eval, ShapeFn shape) {
   RelaxDev& D = R.D;
   int32_t h_running = 0;
+  const int gr = R.graph_rounds;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
+  int r0 = 0;  // first round of the plain launches
   if (!g_trace && G.begin(st)) {
     hipStream_t cs = G.cs;
-    for (int r = 0; r < max_rounds; r += kGraphRounds) {
+    bool fallback = false;
+    int r = 0;
+    for (; r < max_rounds; r += gr) {
       const int sh = shape();
       if (!G.ex[sh]) {
+        // capture this shape's rounds; a capture or instantiation that fails
+        // leaves nothing enqueued and hands the rounds to plain launches
         hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return CD_ERR_HIP;
-        for (int q = 0; q < kGraphRounds; ++q) launch_round(R, cs, hist32, sh, eval);
-        if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return CD_ERR_HIP;
-        const hipError_t ie = hipGraphInstantiate(&G.ex[sh], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          fallback = true;
+          break;
+        }
+        for (int q = 0; q < gr; ++q) launch_round(R, cs, hist32, sh, eval);
+        const hipError_t ce = hipStreamEndCapture(cs, &g);
+        const hipError_t ie =
+            (ce == hipSuccess && g) ? hipGraphInstantiate(&G.ex[sh], g, nullptr, nullptr, 0)
+                                    : hipErrorUnknown;
+        if (g) (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
           G.ex[sh] = nullptr;
-          return CD_ERR_HIP;
+          (void)hipGetLastError();  // the failed capture's error is handled here
+          fallback = true;
+          break;
         }
       }
-      g_last_rounds = r + kGraphRounds;
+      g_last_rounds = r + gr;
       if (hipGraphLaunch(G.ex[sh], cs) != hipSuccess ||
           hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, cs) !=
               hipSuccess ||
@@ -2321,12 +2382,14 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Rou
       R.running = h_running;
       if (h_running <= 0) break;
     }
-    return G.end(st);
+    const int rc = G.end(st);
+    if (rc || !fallback) return rc;
+    r0 = r;
   }
-  for (int r = 0; r < max_rounds; ++r) {
+  for (int r = r0; r < max_rounds; ++r) {
     g_last_rounds = r + 1;
     launch_round(R, st, hist32, shape(), eval);
-    if ((r & 7) == 7) {
+    if ((r + 1) % gr == 0) {
       if (hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
           hipSuccess)
         return CD_ERR_HIP;
@@ -2441,10 +2504,17 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   // path a CG iteration costs a pair pass like an L-BFGS iteration, and
   // L-BFGS, which keeps its curvature pairs across rounds, is as fast
   const bool plain = o.precision == CD_FP64;
+  const RelaxSched sched = kRelaxScheds[relax_sched_index(o.precision, o.coords, n, ntot)];
+  R.graph_rounds = sched.graph_rounds;
+  R.wide_blocks = sched.wide_blocks;
   D.tu = o.coords == CD_COORDS_TU;
   D.tu_rmin = 1e-3 * D.sigma;
-  // the Newton steps work in (x, y) and angle coordinates: none in (t, u)
-  D.polish = !D.tu && (o.polish == CD_POLISH_NEWTON || (o.polish == CD_POLISH_DEFAULT && plain));
+  // the Newton steps work in (x, y) and angle coordinates: none in (t, u); a
+  // tuned schedule may flip the path's default polish
+  bool newton_default = plain;
+  if (sched.polish == kOtherPolish) newton_default = !newton_default;
+  D.polish = !D.tu && (o.polish == CD_POLISH_NEWTON ||
+                       (o.polish == CD_POLISH_DEFAULT && newton_default));
   D.max_cg = o.max_polish_iter > 0 ? o.max_polish_iter : 500;
   D.newton_tol = o.newton_tol > 0.0 ? o.newton_tol : (plain ? 3e-2 : 3e-5) / (h * h);
   D.cg_eta = o.cg_eta > 0.0 ? o.cg_eta : (plain ? 1e-2 : 0.0);  // 0: adaptive forcing
@@ -2456,7 +2526,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   // a whole number of graph replays, so that replayed and one-by-one rounds
   // stop at the same round
   const int max_rounds =
-      (4 * max_iter_eff + 64 + newton_rounds + kGraphRounds - 1) / kGraphRounds * kGraphRounds;
+      (4 * max_iter_eff + 64 + newton_rounds + R.graph_rounds - 1) / R.graph_rounds *
+      R.graph_rounds;
 
   std::vector<int2> blk;
   blk.reserve(R.nblk);
@@ -2549,10 +2620,10 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     bool rebuild = false;
     RelaxDev Df = D;
     Df.eval_all = 1;
-    // 16-wave model blocks when the running patches hold fewer than 512
-    // blocks (estimated from the running count)
+    // 16-wave model blocks when the running patches hold fewer than
+    // wide_blocks blocks (estimated from the running count)
     auto wide_shape = [&]() {
-      return (int)((int64_t)R.running * D.nblk < (int64_t)512 * n_patches);
+      return (int)((int64_t)R.running * D.nblk < R.wide_blocks * n_patches);
     };
     auto model_on = [&](int all, hipStream_t s, int wide) {
       RelaxDev E = D;
@@ -2646,6 +2717,49 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   rc = hip_status(hipGetLastError());
   if (rc) return rc;
   return hip_status(hipStreamSynchronize(st));
+}
+
+// Relax schedule tuning: every schedule of kRelaxScheds relaxes the caller's
+// batch once (outputs discarded; the first schedule once more beforehand, so
+// that one-time start-up costs do not count), timed on the host around the
+// synchronising call; the fastest is kept for later calls with the same
+// device, precision, coordinates, n and floor(log2(total actives)).
+int relax_autotune(const double* x, const double* y, int64_t n, int32_t n_patches,
+                   const int32_t* patch_ptr, const int32_t* active_idx, const double* x_start,
+                   const double* y_start, const cd_relax_opts* opts, void* ws, size_t ws_bytes,
+                   void* stream, int32_t* choice_out, double* times_out) {
+  if (!choice_out || !opts || !patch_ptr || n_patches < 1) return CD_ERR_INVALID_ARG;
+  const int64_t ntot = patch_ptr[n_patches];
+  double best_t = 0.0;
+  int best = 0;
+  int rc = CD_OK;
+  for (int k = -1; k < kNumRelaxScheds && !rc; ++k) {
+    g_force_sched = k < 0 ? 0 : k;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = relax_subdomains(x, y, n, n_patches, patch_ptr, active_idx, x_start, y_start, opts,
+                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws,
+                          ws_bytes, stream);
+    const double dt =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (k < 0 || rc) continue;
+    if (times_out) times_out[k] = dt;
+    if (k == 0 || dt < best_t) {
+      best = k;
+      best_t = dt;
+    }
+  }
+  g_force_sched = -1;
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_rtune_mu);
+    g_rtuned[relax_key(opts->precision, opts->coords, n, ntot)] = best;
+  }
+  const RelaxSched& sc = kRelaxScheds[best];
+  choice_out[0] = best;
+  choice_out[1] = (int32_t)std::min<int64_t>(sc.wide_blocks, INT32_MAX);
+  choice_out[2] = sc.graph_rounds;
+  choice_out[3] = sc.polish;
+  return CD_OK;
 }
 
 // Greedy commit of relaxed candidates.  Candidates with a negative energy

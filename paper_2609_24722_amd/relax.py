@@ -144,6 +144,37 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     return RelaxResult(xo, yo, dE, es, gt, it, stt, pst)
 
 
+def relax_autotune(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3, max_iter=None,
+                   lbfgs_m=16, sigma=0.0, boundary=None, coords=COORDS_XY):
+    """Time every relax schedule on this batch and keep the fastest for later
+    relax_subdomains calls with the same precision, coordinates, n and
+    log2(total actives) (see coulomb_disk.h).  Returns (index, wide-block
+    count, rounds per graph replay, polish flag, seconds per candidate)."""
+    if max_iter is None:
+        max_iter = 300 if precision == MIXED else 8000
+    dev = ops._chk(x, y)
+    n = x.numel()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    P = ptr.size - 1
+    L = ops.lib()
+    if not getattr(L, "_rtune_bound", False):
+        L.relax_autotune.restype = ctypes.c_int
+        L.relax_autotune.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                     ctypes.POINTER(RelaxOpts), _vp, ctypes.c_size_t, _vp, _vp, _vp]
+        L._rtune_bound = True
+    o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), 0, float(gtol), 0.0, 0.0, 0.0, float(sigma),
+                  boundary.data_ptr() if boundary is not None else None, 0, 0, 0.0, 0.0, None, 0.0, int(coords))
+    ws, nb = ops.workspace(ops.OP_RELAX, n, int(precision), dev, n_patches=P, total_active=int(ptr[-1]))
+    out = (ctypes.c_int32 * 4)()
+    times = (ctypes.c_double * 9)()
+    ops.check(L.relax_autotune(x.data_ptr(), y.data_ptr(), n, P, ptr.ctypes.data, idx.data_ptr(),
+                               x_start.data_ptr() if x_start is not None else None,
+                               y_start.data_ptr() if y_start is not None else None, ctypes.byref(o),
+                               ws.data_ptr(), nb, ops.stream_ptr(dev), ctypes.cast(out, _vp),
+                               ctypes.cast(times, _vp)), "relax_autotune")
+    return int(out[0]), int(out[1]), int(out[2]), int(out[3]), list(times)
+
+
 def commit_patches(x, y, ptr, idx, x_rel, y_rel, order_key):
     """Greedy commit (see coulomb_disk.h): updates x, y in place; returns
     (committed host int32 [P], dE_commit host float64 [P])."""

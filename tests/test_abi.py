@@ -138,3 +138,15 @@ def test_noalloc_refuses_sizes_beyond_its_scratch(L):
     assert f(d, d, 830721, 0, d, d, None, None) == -6
     assert f(d, d, 1 << 27, 0, d, d, None, None) == -1   # beyond any plan
     assert f(None, d, 10, 0, d, d, None, None) == -1
+
+
+def test_relax_autotune_argument_errors(L):
+    vp = ctypes.c_void_p
+    f = L.relax_autotune
+    f.restype = ctypes.c_int
+    f.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, vp, vp]
+    import numpy as np
+    ptr = np.array([0, 10], dtype=np.int32)
+    fake = vp(256)
+    assert f(fake, fake, 100, 1, ptr.ctypes.data, fake, None, None, fake, fake, 1 << 20, None, None, None) == -1
+    assert f(fake, fake, 100, 0, ptr.ctypes.data, fake, None, None, fake, fake, 1 << 20, None, fake, None) == -1

@@ -272,3 +272,24 @@ def test_graph_rounds_match_plain_launches(dev, prec, monkeypatch):
     for a, b, c, f in zip(*runs, fields):
         assert torch.equal(a, b) and torch.equal(a, c), f
     assert (runs[0][6] == 0).all()
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_relax_autotune_then_relax(dev, prec):
+    # a batch with an n no other test uses (the tuned schedule is kept
+    # process-wide per n): every candidate runs, the choice is valid, and a
+    # relax with the tuned schedule passes the oracle's endpoint checks
+    n = 2999
+    x, y = W.warped_lattice(n, 0.1, 71)
+    centres, _ = W.patch_draws(n, 6, 10, 20, 72)
+    sizes = np.array([1, 40, 64, 65, 200, 400], dtype=np.int32)
+    xt, yt = t(x, dev), t(y, dev)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    print(f"[case] relax autotune prec={prec}", flush=True)
+    k, wide, rounds, pol, times = R.relax_autotune(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
+    print(f"[tune] choice {k} wide {wide} rounds {rounds} polish {pol} times {np.round(times, 4)}")
+    assert 0 <= k < 9 and rounds in (4, 8, 16, 32) and pol in (-1, 1)
+    assert all(tt > 0 for tt in times) and times[k] == min(times)
+    res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
+    torch.cuda.synchronize()
+    check_endpoints(x, y, ptr, idx.cpu().numpy(), res, 1e-6, f"tuned-{prec}")
