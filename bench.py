@@ -55,6 +55,7 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak
 FP32_UNPACKED_FMA_TFLOPS = 108.0  # unpacked v_fma_f32 issue: 5.1-5.4e13 lane-ops/s x 2 flops
 FLOPS_EF = 13                # energy+forces: 2 sub, 3 r^2, 1 rsqrt, 1 add, 2 r^-3, 4 FMA
+FLOPS_EF_EXEC = 17           # executed per unordered pair: the same plus the j side's two FMAs
 FLOPS_HVP = 24
 FLOPS_RIESZ = 15             # Riesz-s: 2 sub, 3 r^2, log2, mul, exp2, 2 energy fma, 1 mul, 4 FMA
 
@@ -147,32 +148,67 @@ def cpu_baseline(x, y, seconds=15.0):
             "value_1_thread": r1 * (n - 1) / d1, "cpu_model": model}
 
 
+def progress(msg):
+    """A progress line on stderr (the result line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def relax_comparison(xt, yt, subset):
     """Workload 4: 256 patches, sizes U{200..5000}, centres seeded, start at the
-    snapshot; gtol 1e-3 on the exact reduced gradient."""
+    snapshot; gtol 1e-3 on the exact reduced gradient.
+
+    Both paths on all 256 patches (the plain FP64 path with its default
+    truncated-Newton polish), the paper's optimiser (L-BFGS, no polish) on the
+    plain path for the first `subset` patches, an ablation (the mixed model
+    with FP64 pairs only), and the comparison at equal energy: from the plain
+    path's endpoints kicked by 0.02 h both paths relax the subset, the patches
+    whose endpoints agree (E_sub to 1e-12, positions within 1e-3 h) are relaxed
+    again as a batch of their own, and only that rerun -- re-checked to the
+    same 1e-12 -- gives the speedup at equal E."""
     import numpy as np
     import torch
     from paper_2609_24722_amd import FP64, MIXED, workloads as W
     from paper_2609_24722_amd import relax as R
     n = xt.numel()
+    h = W.spacing(n)
     centres, sizes = W.patch_draws(n, 256, 200, 5000, 1104)
     ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    st = lambda r: np.bincount(r.status.cpu().numpy(), minlength=4).tolist()
 
-    def run(pp, ii, prec):
+    def run(pp, ii, prec, sx=None, sy=None, **kw):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        r = R.relax_subdomains(xt, yt, pp, ii, precision=prec, gtol=1e-3)
+        r = R.relax_subdomains(xt, yt, pp, ii, sx, sy, precision=prec, gtol=1e-3, **kw)
         torch.cuda.synchronize()
-        return time.perf_counter() - t, r
+        dt = time.perf_counter() - t
+        progress(f"relax {'mixed' if prec == MIXED else 'fp64'} {pp.size - 1} patches {kw or ''}: {dt:.2f} s")
+        return dt, r
+
+    def agree(pp, ra, rb):
+        """per patch: relative E_sub difference and largest displacement (units of h)"""
+        ea, eb = ra.e_sub.cpu().numpy(), rb.e_sub.cpu().numpy()
+        xa, ya, xb, yb = (a.cpu().numpy() for a in (ra.x, ra.y, rb.x, rb.y))
+        disp = np.array([np.hypot(xa[pp[p]:pp[p + 1]] - xb[pp[p]:pp[p + 1]],
+                                  ya[pp[p]:pp[p + 1]] - yb[pp[p]:pp[p + 1]]).max() for p in range(pp.size - 1)])
+        return np.abs(ea - eb) / np.abs(eb), disp / h
+
+    def sub_batch(pp, ii, keep):
+        """the patches `keep` of batch (pp, ii) as a batch of their own"""
+        ih = ii.cpu().numpy()
+        sel = np.concatenate([np.arange(pp[p], pp[p + 1]) for p in keep])
+        return R.offsets(np.diff(pp)[keep]), torch.tensor(ih[sel], device=xt.device), sel
 
     t_all, r_all = run(ptr, idx, MIXED)
+    t_all_fp, r_all_fp = run(ptr, idx, FP64)
+    rel256, disp256 = agree(ptr, r_all, r_all_fp)
+    same256 = (rel256 <= 1e-12) & (disp256 <= 1e-3)
     ps = ptr[:subset + 1].copy()
     ids = idx[:int(ps[-1])].contiguous()
     t_mix, r_mix = run(ps, ids, MIXED)
     t_fp, r_fp = run(ps, ids, FP64)
-    h = W.spacing(n)
-    # same basin: both paths from the plain path's endpoints kicked by 0.02 h
-    # (seeded), so that they end in one minimum and the times compare at equal E
+    t_fp_lb, r_fp_lb = run(ps, ids, FP64, polish=R.POLISH_LBFGS)
+    t_abl, r_abl = run(ps, ids, MIXED, inner_tol=1e300)
+    # equal energy: common near-minimum starts (the plain path's endpoints kicked by 0.02 h)
     rng = np.random.default_rng(1204)
     m = int(ps[-1])
     bx = r_fp.x.cpu().numpy() + rng.normal(0.0, 0.02 * h, m)
@@ -180,35 +216,22 @@ def relax_comparison(xt, yt, subset):
     rr = np.hypot(bx, by)
     bx, by = np.where(rr > 1, bx / rr, bx), np.where(rr > 1, by / rr, by)
     sxt, syt = torch.tensor(bx, device=xt.device), torch.tensor(by, device=xt.device)
-
-    def run_from(prec):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = R.relax_subdomains(xt, yt, ps, ids, sxt, syt, precision=prec, gtol=1e-3)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, r
-
-    tb_mix, rb_mix = run_from(MIXED)
-    tb_fp, rb_fp = run_from(FP64)
-    # ablation: the mixed path's model with FP64 pairs throughout (no FP32 stage)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    r_abl = R.relax_subdomains(xt, yt, ps, ids, precision=MIXED, gtol=1e-3, inner_tol=1e300)
-    torch.cuda.synchronize()
-    t_abl = time.perf_counter() - t
-    ebm, ebf = rb_mix.e_sub.cpu().numpy(), rb_fp.e_sub.cpu().numpy()
-    dbx = np.array([np.hypot(rb_mix.x.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.x.cpu().numpy()[ps[p]:ps[p + 1]],
-                             rb_mix.y.cpu().numpy()[ps[p]:ps[p + 1]] - rb_fp.y.cpu().numpy()[ps[p]:ps[p + 1]]).max()
-                    for p in range(subset)])
-    bsame = dbx < 1e-3 * h
-    brel = np.abs(ebm - ebf) / np.abs(ebf)
-    em, ef = r_mix.e_sub.cpu().numpy(), r_fp.e_sub.cpu().numpy()
-    xm, ym, xf, yf = (a.cpu().numpy() for a in (r_mix.x, r_mix.y, r_fp.x, r_fp.y))
-    disp = np.array([np.hypot(xm[ps[p]:ps[p + 1]] - xf[ps[p]:ps[p + 1]],
-                              ym[ps[p]:ps[p + 1]] - yf[ps[p]:ps[p + 1]]).max() for p in range(subset)])
-    same = disp < 1e-3 * h
-    rel = np.abs(em - ef) / np.abs(ef)
-    st = lambda r: np.bincount(r.status.cpu().numpy(), minlength=4).tolist()
+    tb_mix, rb_mix = run(ps, ids, MIXED, sxt, syt)
+    tb_fp, rb_fp = run(ps, ids, FP64, sxt, syt)
+    brel, bdisp = agree(ps, rb_mix, rb_fp)
+    keep = np.nonzero((brel <= 1e-12) & (bdisp <= 1e-3))[0]
+    eq = {"patches_same_minimum": int(keep.size), "patches_tried": subset}
+    if keep.size:
+        pk, ik, sel = sub_batch(ps, ids, keep)
+        kx, ky = sxt[sel].contiguous(), syt[sel].contiguous()
+        te_mix, re_mix = run(pk, ik, MIXED, kx, ky)
+        te_fp, re_fp = run(pk, ik, FP64, kx, ky)
+        erel, edisp = agree(pk, re_mix, re_fp)
+        ok = (erel <= 1e-12) & (edisp <= 1e-3)
+        eq.update({"mixed_s": te_mix, "fp64_s": te_fp, "speedup_at_equal_E": te_fp / te_mix,
+                   "rerun_patches_within_1e-12": int(ok.sum()), "rerun_patches": int(keep.size),
+                   "max_rel_energy_diff": float(erel.max()), "status_mixed": st(re_mix),
+                   "status_fp64": st(re_fp)})
     return {
         "workload": f"N={n} warped lattice (sigma 0.02 h); 256 patches of the k nearest charges to "
                     f"seeded centres, k ~ U{{200..5000}} (total {int(ptr[-1])} actives); start = snapshot; "
@@ -216,28 +239,52 @@ def relax_comparison(xt, yt, subset):
         "mixed_s_per_cycle_256": t_all,
         "mixed_status_256": st(r_all),
         "mixed_exact_passes_mean_256": float(r_all.iters[:, 1].float().mean().item()),
+        "fp64_s_256": t_all_fp,
+        "fp64_status_256": st(r_all_fp),
+        "fp64_newton_steps_mean_256": float(r_all_fp.polish[:, 0].float().mean().item()),
+        "fp64_exact_passes_mean_256": float(r_all_fp.iters[:, 1].float().mean().item()),
+        "speedup_256_not_at_equal_E": t_all_fp / t_all,
+        "same_minimum_patches_256": int(same256.sum()),
+        "median_rel_energy_diff_256": float(np.median(rel256)),
         "subset_patches": subset,
         "subset_mixed_s": t_mix,
         "subset_fp64_s": t_fp,
-        "subset_speedup": t_fp / t_mix,
-        "subset_status_mixed": st(r_mix),
-        "subset_status_fp64": st(r_fp),
-        "same_minimum_patches": int(same.sum()),
-        "same_minimum_max_rel_energy_diff": float(rel[same].max()) if same.any() else None,
-        "all_patches_median_rel_energy_diff": float(np.median(rel)),
-        "mean_dE_mixed": float(r_mix.dE.mean().item()),
-        "mean_dE_fp64": float(r_fp.dE.mean().item()),
+        "subset_fp64_lbfgs_s": t_fp_lb,
+        "subset_status": {"mixed": st(r_mix), "fp64": st(r_fp), "fp64_lbfgs": st(r_fp_lb)},
         "ablation_fp64_model_s": t_abl,
         "ablation_status": st(r_abl),
-        "same_basin": {
-            "start": "the plain path's endpoints of the subset, kicked by N(0, (0.02 h)^2) per coordinate",
-            "mixed_s": tb_mix, "fp64_s": tb_fp, "speedup": tb_fp / tb_mix,
-            "same_minimum_patches": int(bsame.sum()),
-            "same_minimum_max_rel_energy_diff": float(brel[bsame].max()) if bsame.any() else None,
-            "max_rel_energy_diff_all": float(brel.max()),
-            "status_mixed": st(rb_mix), "status_fp64": st(rb_fp),
-        },
+        "equal_E": dict(eq, start="the plain path's endpoints of the subset, kicked by N(0, (0.02 h)^2) "
+                                  "per coordinate; speedup from the rerun of the patches that agreed",
+                        all_subset_mixed_s=tb_mix, all_subset_fp64_s=tb_fp,
+                        all_subset_speedup_not_at_equal_E=tb_fp / tb_mix,
+                        all_subset_patches_disagreeing=int(subset - keep.size)),
     }
+
+
+def relax_tuning(xt, yt, dev, n, defect_T):
+    """relax_autotune on workload 4's batch and, in an untimed warm-up
+    defect-targeted cycle, on the first batch of each size class (log2 of its
+    total actives); returns the choices."""
+    import torch
+    from paper_2609_24722_amd import MIXED, workloads as W
+    from paper_2609_24722_amd import relax as R
+    from paper_2609_24722_amd.cycle import defect_cycle
+    centres, sizes = W.patch_draws(n, 256, 200, 5000, 1104)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    choices = {"workload4": R.relax_autotune(xt, yt, ptr, idx, precision=MIXED, gtol=1e-3)[:4]}
+    x, y = W.workload(3, n)
+    cx = torch.tensor(x, device=dev)
+    cy = torch.tensor(y, device=dev)
+    seen = {}
+
+    def tune(b, sel, zx, zy, rz, pp, ii):
+        key = int(pp[-1]).bit_length() - 1
+        if key not in seen:
+            seen[key] = R.relax_autotune(cx, cy, pp, ii, precision=MIXED, gtol=1e-3)[:4]
+
+    defect_cycle(cx, cy, T=defect_T, precision=MIXED, inspect=tune)
+    choices["defect_cycle_by_log2_actives"] = {str(k): v for k, v in sorted(seen.items())}
+    return choices
 
 
 def relax_only(dev, prec):
@@ -396,6 +443,9 @@ def main():
     ap.add_argument("--border-sweep", type=int, default=0, metavar="N",
                     help="one defect-targeted cycle per N_b around Eq. 4 (border-interior split) at N "
                          "charges, plus the hard wall, and exit")
+    ap.add_argument("--tune-relax", action="store_true",
+                    help="pick relax schedules with relax_autotune (workload 4, and per batch size class "
+                         "in an untimed warm-up cycle) before the relax and cycle measurements")
     ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
@@ -486,6 +536,10 @@ def main():
                           "which this build does not emit; unpacked FP32 FMA issue reaches about "
                           f"{FP32_UNPACKED_FMA_TFLOPS} TFLOP/s on gfx950 (measured issue rate)"),
             "frac_of_unpacked_fma": achieved / FP32_UNPACKED_FMA_TFLOPS,
+            # each unordered pair is evaluated once, with about 17 flops of work
+            # (2 sub, 3 r^2, rsqrt, add, 2 r^-3, 4 FMA for i, 4 FMA for j)
+            "flops_executed_per_unordered_pair": FLOPS_EF_EXEC,
+            "frac_executed": FLOPS_EF_EXEC * (pairs / 2) / (kern_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
         },
     }
     if not args.no_extra:
@@ -507,10 +561,15 @@ def main():
                            "alg_tflops": FLOPS_RIESZ * pairs / (k * 1e-3) / 1e12}
         out["extra"] = extra
     if not args.no_relax:
+        tuned = relax_tuning(xt, yt, dev, n, args.defect_T) if args.tune_relax else None
         out["relax"] = relax_comparison(xt, yt, args.relax_subset)
+        out["relax"]["schedule"] = tuned if tuned else "library default (not tuned)"
     if not args.no_relax and not args.no_defect:  # --no-relax skips every relax measurement
+        progress("defect-targeted cycle")
         out["defect_cycle"] = defect_cycle_run(dev, n, args.defect_kappa, MIXED, args.defect_T)
+        progress(f"defect-targeted cycle: {out['defect_cycle']['wall_s']:.2f} s")
     if not args.no_cpu:
+        progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(x, y)
     print(json.dumps(out), flush=True)
 

@@ -327,6 +327,13 @@ int defect_zones(const double* x, const double* y, const double* e, int64_t n, i
                  double* rz, int32_t* centre_idx, double* stats, int32_t* defect_idx, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* The radius of a disk about a point of the unit disk that holds `count` of
+ * the n charges at their mean density (n / pi): sqrt(count / n), rounded
+ * once per operation; the r_lo and r_hi of cd_zone_opts for zones of a given
+ * size (Sec. II.C: subdomains of a few hundred to a few thousand charges).
+ * 0 for n < 1 or count < 0.  Host function, no device work. */
+double zone_radius_holding(int64_t n, int64_t count);
+
 /* Active sets of zones (Sec. II.C step 4): zone p holds every charge j with
  * (dx*dx) + (dy*dy) <= rz[p]*rz[p], dx = x[j] - cx[p], dy = y[j] - cy[p], each
  * operation rounded once in FP64, listed in increasing index order.
@@ -363,6 +370,14 @@ int zone_batches(const double* cx, const double* cy, const double* rz, int32_t n
  * interior radius of Eq. 5, 1 - 1/(2 sqrt(N)).  Host code. */
 int32_t border_count(int64_t n);
 double border_sigma0(int64_t n);
+
+/* The interior radius over a cycle (Sec. II.B: it rises from the value of
+ * Eq. 5 to 1; the paper gives the end points, not the law): stage k of
+ * `stages` has sigma_start + (sigma_end - sigma_start) (k / stages), k clamped
+ * to [0, stages]; sigma_start <= 0 takes border_sigma0(n); stages <= 0 gives
+ * sigma_end.  Host function, no device work. */
+double border_sigma_ramp(int64_t n, int32_t k, int32_t stages, double sigma_start,
+                         double sigma_end);
 
 /* Boundary charges: flags[n] (device int32) = 1 for the nb charges farthest
  * from the centre by (x*x) + (y*y) (each operation rounded once in FP64),
@@ -413,6 +428,16 @@ int voronoi_coordination(const double* x, const double* y, int64_t n, int32_t* z
  * also taking |r| >= 1.  Does not synchronise. */
 int radial_histogram(const double* x, const double* y, int64_t n, int32_t nbins, int32_t* counts,
                      void* stream);
+
+/* Statistics of a voronoi_coordination result (Sec. III: the coordination
+ * fractions and the mean bond-orientational order), into out (device double
+ * [9]): out[0..4] the fractions P(z) of the bounded cells with z = 4..8,
+ * out[5] the mean of |psi_6| over the bounded cells (0 when psi6 is NULL or
+ * no cell is bounded), out[6] the number of bounded cells (z >= 0), out[7]
+ * of hull charges (z = -2), out[8] of unresolved cells (z = -1).  One
+ * workgroup sums in a fixed order, so the result is reproducible.  Does not
+ * synchronise. */
+int structure_stats(const int32_t* z, const double* psi6, int64_t n, double* out, void* stream);
 
 /* Greedy commit of relaxed candidates (perturb-and-relax cycles): the
  * candidates whose snapshot energy change order_key[p] (host [P], e.g. the dE

@@ -21,6 +21,9 @@ def _lib():
         L.border_count.argtypes = [ctypes.c_int64]
         L.border_sigma0.restype = ctypes.c_double
         L.border_sigma0.argtypes = [ctypes.c_int64]
+        L.border_sigma_ramp.restype = ctypes.c_double
+        L.border_sigma_ramp.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_double]
         L.border_split.restype = ctypes.c_int
         L.border_split.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p]
@@ -44,10 +47,10 @@ def sigma0(n: int) -> float:
     return float(_lib().border_sigma0(int(n)))
 
 
-def sigma_ramp(k: int, stages: int, n: int) -> float:
-    """Interior radius of stage k = 0..stages, linear from sigma0 to 1."""
-    s0 = sigma0(n)
-    return s0 + (1.0 - s0) * (k / stages) if stages > 0 else 1.0
+def sigma_ramp(k: int, stages: int, n: int, sigma_start: float = 0.0, sigma_end: float = 1.0) -> float:
+    """Interior radius of stage k = 0..stages, linear from sigma_start (Eq. 5's
+    value when 0) to sigma_end."""
+    return float(_lib().border_sigma_ramp(int(n), int(k), int(stages), float(sigma_start), float(sigma_end)))
 
 
 def border_split(x, y, nb: int):

@@ -201,6 +201,14 @@ double border_sigma0(int64_t n) {
   if (n < 1) return 1.0;
   return 1.0 - 1.0 / (2.0 * sqrt((double)n));
 }
+
+double border_sigma_ramp(int64_t n, int32_t k, int32_t stages, double sigma_start,
+                         double sigma_end) {
+  const double s0 = sigma_start > 0.0 ? sigma_start : border_sigma0(n);
+  if (stages <= 0) return sigma_end;
+  const int32_t kk = k < 0 ? 0 : (k > stages ? stages : k);
+  return s0 + (sigma_end - s0) * ((double)kk / (double)stages);
+}
 #pragma clang fp contract(on)
 
 int border_split(const double* x, const double* y, int64_t n, int32_t nb, int32_t* flags,

@@ -339,6 +339,55 @@ __global__ __launch_bounds__(64) void k_voronoi(const double* __restrict__ x,
   }
 }
 
+// Statistics of a coordination result in one workgroup: per thread a strided
+// pass in index order, then a tree over the threads, so the sums do not
+// depend on timing.  out[0..4]: fractions of the bounded cells with z = 4..8;
+// out[5]: mean |psi_6| over the bounded cells; out[6..8]: the counts of
+// bounded cells, hull charges and unresolved cells.
+__global__ __launch_bounds__(kScanT) void k_structure_stats(const int32_t* __restrict__ z,
+                                                            const double* __restrict__ psi6, int n,
+                                                            double* __restrict__ out) {
+  __shared__ double s_abs[kScanT];
+  __shared__ int32_t s_cnt[8][kScanT];
+  const int t = threadIdx.x;
+  int32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // z = 4..8, bounded, hull, unresolved
+  double a = 0.0;
+  for (int i = t; i < n; i += kScanT) {
+    const int zi = z[i];
+    if (zi >= 0) {
+      ++c[5];
+      if (zi >= 4 && zi <= 8) ++c[zi - 4];
+      if (psi6) {
+        const double re = psi6[2 * i], im = psi6[2 * i + 1];
+        a += sqrt(re * re + im * im);
+      }
+    } else if (zi == -2) {
+      ++c[6];
+    } else {
+      ++c[7];
+    }
+  }
+  s_abs[t] = a;
+  for (int k = 0; k < 8; ++k) s_cnt[k][t] = c[k];
+  __syncthreads();
+  for (int w = kScanT / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      s_abs[t] += s_abs[t + w];
+      for (int k = 0; k < 8; ++k) s_cnt[k][t] += s_cnt[k][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int32_t b = s_cnt[5][0];
+    const double inv = b > 0 ? 1.0 / (double)b : 0.0;
+    for (int k = 0; k < 5; ++k) out[k] = b > 0 ? (double)s_cnt[k][0] * inv : 0.0;
+    out[5] = b > 0 && psi6 ? s_abs[0] / (double)b : 0.0;
+    out[6] = (double)b;
+    out[7] = (double)s_cnt[6][0];
+    out[8] = (double)s_cnt[7][0];
+  }
+}
+
 #pragma clang fp contract(off)
 __global__ void k_radial(const double* __restrict__ x, const double* __restrict__ y, int n,
                          int nbins, int32_t* __restrict__ counts) {
@@ -439,6 +488,13 @@ int radial_histogram(const double* x, const double* y, int64_t n, int32_t nbins,
   hipLaunchKernelGGL(k_fill_int, dim3((nbins + 255) / 256), dim3(256), 0, st, counts, nbins, 0);
   hipLaunchKernelGGL(k_radial, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, (int)n,
                      nbins, counts);
+  return hip_status(hipGetLastError());
+}
+
+int structure_stats(const int32_t* z, const double* psi6, int64_t n, double* out, void* stream) {
+  if (!z || !out || n < 1 || n > (1 << 26)) return CD_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_structure_stats, dim3(1), dim3(kScanT), 0, (hipStream_t)stream, z, psi6,
+                     (int)n, out);
   return hip_status(hipGetLastError());
 }
 

@@ -214,6 +214,11 @@ bool zones_conflict(double ax, double ay, double ar, double bx, double by, doubl
 
 extern "C" {
 
+double zone_radius_holding(int64_t n, int64_t count) {
+  if (n < 1 || count < 0) return 0.0;
+  return sqrt((double)count / (double)n);
+}
+
 int defect_zones(const double* x, const double* y, const double* e, int64_t n, int32_t n_zones,
                  const double* draws, const cd_zone_opts* opts, double* cx, double* cy,
                  double* rz, int32_t* centre_idx, double* stats, int32_t* defect_idx, void* ws,

@@ -101,8 +101,8 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
     n = x.numel()
     dev = x.device
     h = W.spacing(n)
-    r_lo = float(np.sqrt(n_lo / n))
-    r_hi = float(np.sqrt(n_hi / n))
+    r_lo = Z.radius_holding(n, n_lo)
+    r_hi = Z.radius_holding(n, n_hi)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     flags = None
@@ -147,7 +147,7 @@ def defect_cycle(x, y, T: int = 1000, cap: int = 256, kappa: float = -1.0, p_def
             inspect(b, sel[keep], cx, cy, rz, ptr, idx)
         sig = 0.0
         if flags is not None:
-            sig = s0 + (sigma_end - s0) * (b / max(1, nb - 1))
+            sig = B.sigma_ramp(b, max(1, nb - 1), n, s0, sigma_end)
         res = R.relax_subdomains(x, y, ptr, idx, precision=precision, gtol=gtol, sigma=sig, boundary=flags,
                                  lbfgs_m=lbfgs_m, **(relax_kw or {}))
         com, dc = R.commit_patches(x, y, ptr, idx, res.x, res.y, res.dE.cpu().numpy())

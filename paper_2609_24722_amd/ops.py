@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libcoulombdisk.so")
  OP_VORONOI, OP_BORDER) = range(11)
 
 _lib = None
-_ws = {}
+_ws = {}    # (device, op, stream) -> [buffer, used under capture]
+_kept = []  # outgrown buffers that a captured graph may still use
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -68,16 +69,25 @@ def check(rc: int, what: str) -> None:
 
 
 def workspace(op: int, n: int, precision: int, device, n_patches: int = 0, total_active: int = 0):
-    """Device scratch for ``op`` (grown on demand, cached per device and op)."""
+    """Device scratch for ``op`` on the current stream: grown on demand and
+    cached per device, op and stream, so calls on different streams never
+    share one.  A buffer that a graph capture has used is never released: when
+    a later call outgrows it, the old buffer stays alive (the captured graph
+    keeps writing to it on every replay) and the call gets a new one."""
     nbytes = int(lib().coulomb_workspace_bytes(op, n, n_patches, total_active, precision))
     if nbytes == 0:
         raise CoulombError(f"invalid sizes for op {op}: n={n}")
-    key = (str(device), op)
-    buf = _ws.get(key)
-    if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        _ws[key] = buf
-    return buf, nbytes
+    stream = torch.cuda.current_stream(device)
+    key = (str(device), op, stream.cuda_stream)
+    ent = _ws.get(key)
+    if ent is None or ent[0].numel() < nbytes:
+        if ent is not None and ent[1]:
+            _kept.append(ent[0])
+        ent = [torch.empty(nbytes, dtype=torch.uint8, device=device), False]
+        _ws[key] = ent
+    if torch.cuda.is_current_stream_capturing():
+        ent[1] = True
+    return ent[0], nbytes
 
 
 def stream_ptr(device=None) -> int:

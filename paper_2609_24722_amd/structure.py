@@ -23,6 +23,8 @@ def _lib():
         L.voronoi_coordination.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.radial_histogram.restype = ctypes.c_int
         L.radial_histogram.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]
+        L.structure_stats.restype = ctypes.c_int
+        L.structure_stats.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp]
         L._structure_bound = True
     return L
 
@@ -49,16 +51,32 @@ def radial_histogram(x, y, nbins: int):
     return counts
 
 
+def stats(z, psi=None):
+    """Host dict of structure_stats over a voronoi() result: P(z) for z = 4..8
+    and mean |psi_6| over the bounded cells, and the cell counts."""
+    dev = z.device
+    if z.dtype != torch.int32 or not z.is_contiguous() or dev.type != "cuda":
+        raise ops.CoulombError("z must be a contiguous device int32 tensor")
+    n = z.numel()
+    p = None
+    if psi is not None:
+        p = torch.view_as_real(psi).contiguous()
+        if p.dtype != torch.float64 or p.numel() != 2 * n or p.device != dev:
+            raise ops.CoulombError("psi must be a device complex128 tensor of length n")
+    out = torch.empty(9, dtype=torch.float64, device=dev)
+    ops.check(_lib().structure_stats(z.data_ptr(), p.data_ptr() if p is not None else None, n, out.data_ptr(),
+                                     ops.stream_ptr(dev)), "structure_stats")
+    o = out.cpu().tolist()
+    return {"P_z": {k: o[k - 4] for k in (4, 5, 6, 7, 8)}, "mean_abs_psi6": o[5], "bounded_cells": int(o[6]),
+            "hull": int(o[7]), "unresolved": int(o[8])}
+
+
 def summary(x, y, nbins: int = 50):
     """Coordination fractions, <|psi_6|>, unresolved cells and radial counts
     (host values) of a configuration."""
     z, psi = voronoi(x, y)
     c = radial_histogram(x, y, nbins)
-    zc = z.cpu()
-    ok = zc >= 0
-    tot = int(ok.sum())
-    frac = {k: float((zc == k).sum()) / max(tot, 1) for k in (4, 5, 6, 7, 8)}
-    return {"n": x.numel(), "bounded_cells": tot, "hull": int((zc == -2).sum()),
-            "unresolved": int((zc == -1).sum()), "P_z": frac,
-            "mean_abs_psi6": float(psi.abs().cpu()[ok].mean()) if tot else 0.0,
+    st = stats(z, psi)
+    return {"n": x.numel(), "bounded_cells": st["bounded_cells"], "hull": st["hull"],
+            "unresolved": st["unresolved"], "P_z": st["P_z"], "mean_abs_psi6": st["mean_abs_psi6"],
             "radial_counts": c.cpu().tolist()}

@@ -43,8 +43,15 @@ def _lib():
         L.zone_batches.restype = ctypes.c_int
         L.zone_batches.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, _vp, _vp]
+        L.zone_radius_holding.restype = ctypes.c_double
+        L.zone_radius_holding.argtypes = [ctypes.c_int64, ctypes.c_int64]
         L._zones_bound = True
     return L
+
+
+def radius_holding(n: int, count: int) -> float:
+    """Radius of a disk that holds `count` of n charges at the mean density."""
+    return float(_lib().zone_radius_holding(int(n), int(count)))
 
 
 def defect_zones(x, y, e, draws, kappa: float = -1.0, p_defect: float = 0.8, r_lo: float = 0.0,

@@ -150,3 +150,27 @@ def test_relax_autotune_argument_errors(L):
     fake = vp(256)
     assert f(fake, fake, 100, 1, ptr.ctypes.data, fake, None, None, fake, fake, 1 << 20, None, None, None) == -1
     assert f(fake, fake, 100, 0, ptr.ctypes.data, fake, None, None, fake, fake, 1 << 20, None, fake, None) == -1
+
+
+def test_host_functions_of_the_method(L):
+    """The host-side arithmetic entry points against the oracle's own
+    definitions (no GPU needed)."""
+    import math
+    from oracle import border as OB
+    L.border_sigma_ramp.restype = ctypes.c_double
+    L.border_sigma_ramp.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_double]
+    L.zone_radius_holding.restype = ctypes.c_double
+    L.zone_radius_holding.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    for n in (7, 1000, 100000):
+        for stages in (1, 4, 44):
+            for k in range(stages + 1):
+                assert L.border_sigma_ramp(n, k, stages, 0.0, 1.0) == OB.sigma_ramp(k, stages, n)
+        assert L.border_sigma_ramp(n, -3, 4, 0.0, 1.0) == OB.sigma0(n)
+        assert L.border_sigma_ramp(n, 9, 4, 0.0, 1.0) == 1.0
+        assert L.border_sigma_ramp(n, 0, 0, 0.5, 0.9) == 0.9
+        # a zone of radius sqrt(c / n) holds c of n charges at density n / pi
+        for c in (0, 200, 4000):
+            r = L.zone_radius_holding(n, c)
+            assert abs(math.pi * r * r * (n / math.pi) - c) <= 1e-12 * max(c, 1)
+    assert L.zone_radius_holding(0, 5) == 0.0 and L.zone_radius_holding(5, -1) == 0.0

@@ -46,3 +46,39 @@ def test_pair_calls_replay_bit_exact(dev, prec):
         other = _calls(x2t, y2t, vy, vx, prec)
         torch.cuda.synchronize()
         assert torch.isfinite(other[2]).all()
+
+
+def test_capture_survives_a_larger_eager_call(dev):
+    """A graph captured on a stream whose workspace already existed, then a
+    larger eager call on that stream (which outgrows the cached workspace),
+    then fresh allocations that would reuse released memory: every replay
+    still matches the eager result bit for bit."""
+    n, n_big = 3000, 40000
+    x, y = W.warped_lattice(n, 0.02, 81)
+    xb, yb = W.warped_lattice(n_big, 0.02, 82)
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+        want = ops.forces(xt, yt, MIXED)
+        s.synchronize()
+        want = [t.clone() for t in want]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            got = ops.forces(xt, yt, MIXED)
+        s.synchronize()
+        xbt, ybt = torch.tensor(xb, device=dev), torch.tensor(yb, device=dev)
+        big = ops.forces(xbt, ybt, MIXED)  # outgrows the stream's workspace
+        s.synchronize()
+        filler = [torch.full((1 << 20,), 7.0, dtype=torch.float64, device=dev) for _ in range(8)]
+        for rep in range(3):
+            for t in got:
+                t.fill_(float("nan"))
+            g.replay()
+            s.synchronize()
+            for k, (a, b) in enumerate(zip(got, want)):
+                assert torch.equal(a, b), (rep, k)
+            assert all(bool((f == 7.0).all()) for f in filler)
+            ops.forces(xbt, ybt, MIXED)
+            s.synchronize()
+        assert torch.isfinite(big[0]).all()
+    torch.cuda.synchronize()

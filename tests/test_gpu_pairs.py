@@ -116,6 +116,9 @@ def test_full_size_workload3_sampled(dev, prec):
     print(f"[err] workload3 prec={prec} E={errE:.2e} e={erre:.2e} F={errF:.2e} F(|r|<0.9)={errFi:.2e} "
           f"H={errH:.2e} euler={euler:.2e} Hr=2F:{homog:.2e}")
     assert errF <= tol["F"] and erre <= tol["e"] and errH <= tol["H"] and errE <= tol["E"]
+    # the interior alone (where forces nearly cancel, so the relative error is
+    # largest) must meet the same bound; the wall charges do not hide it
+    assert inner.sum() >= 200 and errFi <= tol["F"]
     assert euler <= max(10 * tol["F"], 1e-12)
     assert homog <= 10 * tol["H"]
     scale = np.sum(np.abs(fx)) + np.sum(np.abs(fy))

@@ -20,6 +20,7 @@ def _cmp(dev, x, y, label):
     z, psi = ST.voronoi(xt, yt)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
+    st = ST.stats(z, psi)
     z = z.cpu().numpy()
     zo = S.voronoi_z(x, y)
     nb = S.voronoi_neighbours(x, y)
@@ -30,6 +31,15 @@ def _cmp(dev, x, y, label):
           f"mismatch={bad.size} {list(zip(bad[:5], z[bad[:5]], zo[bad[:5]]))}", flush=True)
     assert bad.size == 0
     assert np.max(np.abs(psi.cpu().numpy() - po)) < 1e-12
+    # the statistics of Sec. III from the oracle's cells, by their definition
+    ok = zo >= 0
+    b = int(ok.sum())
+    assert st["bounded_cells"] == b and st["hull"] == int((zo == -2).sum())
+    assert st["unresolved"] == int((zo == -1).sum())
+    for k in (4, 5, 6, 7, 8):
+        assert abs(st["P_z"][k] - (zo == k).sum() / b) <= 2.3e-16 * max(1.0, st["P_z"][k] * 4)
+    want = float(np.abs(po[ok]).mean())
+    assert abs(st["mean_abs_psi6"] - want) <= 1e-12 * want
 
 
 @pytest.mark.parametrize("case", ["lattice2000", "lattice20000", "uniform3000", "ring", "wall_ring"])
