@@ -231,9 +231,12 @@ typedef struct {
                                 interior charges starting within 1e-3 sigma of the centre
                                 keep (x, y).  Boundary charges move by their angle (Eq. 10)
                                 either way.  No Newton polish in (t, u) (L-BFGS only). */
+  int32_t launch;            /* CD_LAUNCH_GRAPH: lock-step rounds replayed from HIP graphs;
+                                CD_LAUNCH_PLAIN: the same kernels launched one by one */
 } cd_relax_opts;
 
 enum { CD_COORDS_XY = 0, CD_COORDS_TU = 1 };
+enum { CD_LAUNCH_GRAPH = 0, CD_LAUNCH_PLAIN = 1 };
 
 enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
 
@@ -257,8 +260,8 @@ enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
  * coulomb_workspace_bytes(CD_OP_RELAX, n, P, patch_ptr[P], opts->precision).
  * Reads a few per-round flags back to the host and synchronises the stream
  * before returning.  The lock-step rounds are replayed from HIP graphs
- * captured on a private stream that follows `stream` (environment variable
- * CD_RELAX_GRAPH=0: the same kernels launched one by one, with identical
+ * captured on a private stream that follows `stream` (opts->launch =
+ * CD_LAUNCH_PLAIN: the same kernels launched one by one, with identical
  * results). */
 int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patches,
                      const int32_t* patch_ptr, const int32_t* active_idx,
@@ -281,8 +284,9 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
  * polish choice changes the optimiser: any endpoint still meets the
  * tolerance).  Arguments as relax_subdomains; choice_out: host int32 [4] =
  * chosen index, wide-block count, rounds per replay, polish (-1 default,
- * 1 the other); times_out (nullable): host double [9], seconds per
- * candidate.  Synchronises the stream. */
+ * 1 the other); times_out (nullable): host double [CD_RELAX_SCHEDULES],
+ * seconds per candidate.  Synchronises the stream. */
+#define CD_RELAX_SCHEDULES 9
 int relax_autotune(const double* x, const double* y, int64_t n, int32_t n_patches,
                    const int32_t* patch_ptr, const int32_t* active_idx, const double* x_start,
                    const double* y_start, const cd_relax_opts* opts, void* ws, size_t ws_bytes,

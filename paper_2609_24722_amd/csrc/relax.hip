@@ -2096,6 +2096,7 @@ struct RPlan {
   // block instead of 8
   int graph_rounds = 8;
   int64_t wide_blocks = 512;
+  bool use_graphs = true;  // rounds replayed from HIP graphs (else launched one by one)
   size_t total;
   RelaxDev D;
   int32_t* hcount;  // [P]
@@ -2236,7 +2237,6 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 // Runs rounds (eval + update) until no patch is running or max rounds.
 // Returns a CD status.
 static int g_last_rounds = 0;
-static bool g_trace = false;  // CD_RELAX_TRACE set: progress lines on stderr
 
 // Relax schedules relax_autotune chooses among (the first is the default):
 // the running-block count below which model blocks take 16 waves, lock-step
@@ -2255,6 +2255,7 @@ constexpr RelaxSched kRelaxScheds[] = {{512, 8, -1},  {0, 8, -1},         {1 << 
                                        {256, 8, -1},  {1024, 8, -1},      {512, 4, -1},
                                        {512, 16, -1}, {512, 32, -1},      {512, 8, kOtherPolish}};
 constexpr int kNumRelaxScheds = sizeof(kRelaxScheds) / sizeof(kRelaxScheds[0]);
+static_assert(kNumRelaxScheds == CD_RELAX_SCHEDULES, "the header states the candidate count");
 using RelaxKey = std::tuple<int, int, int, int64_t, int>;  // device, precision, coords, n, log2 total
 static std::mutex g_rtune_mu;
 static std::map<RelaxKey, int> g_rtuned;
@@ -2280,17 +2281,15 @@ static int relax_sched_index(int precision, int coords, int64_t n, int64_t ntot)
 // on a private stream, which follows the caller's stream through events (a
 // caller's default stream cannot be captured), and replayed until no patch
 // runs.  The kernels and their arguments are those of the plain launches, so
-// the results are the same bit for bit.  CD_RELAX_GRAPH=0 selects the plain
-// launches; when a graph cannot be captured or instantiated the rounds go on
-// as plain launches.
+// the results are the same bit for bit.  The launch option CD_LAUNCH_PLAIN
+// selects the plain launches; when a graph cannot be captured or
+// instantiated the rounds go on as plain launches.
 struct RoundGraphs {
   hipStream_t cs = nullptr;
   hipEvent_t ev = nullptr;
   hipGraphExec_t ex[2] = {nullptr, nullptr};
   bool ok = false;
   bool begin(hipStream_t st) {
-    const char* e = getenv("CD_RELAX_GRAPH");
-    if (e && e[0] == '0') return false;
     if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
     if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
     if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
@@ -2346,7 +2345,7 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Rou
   const int gr = R.graph_rounds;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
   int r0 = 0;  // first round of the plain launches
-  if (!g_trace && G.begin(st)) {
+  if (R.use_graphs && G.begin(st)) {
     hipStream_t cs = G.cs;
     bool fallback = false;
     int r = 0;
@@ -2396,7 +2395,6 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Rou
       if (hipStreamSynchronize(st) != hipSuccess) return CD_ERR_HIP;
       R.running = h_running;
       if (h_running <= 0) break;
-      if (g_trace && (r & 255) == 255) fprintf(stderr, "[relax] lock-step round %d: %d running\n", r + 1, h_running);
     }
   }
   return hip_status(hipGetLastError());
@@ -2468,7 +2466,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     return CD_ERR_INVALID_ARG;
   if (o.polish < CD_POLISH_DEFAULT || o.polish > CD_POLISH_LBFGS || o.max_polish_iter < 0 ||
       !(o.newton_tol >= 0.0) || !(o.cg_eta >= 0.0 && o.cg_eta < 1.0) || !(o.trust_radius >= 0.0) ||
-      (o.coords != CD_COORDS_XY && o.coords != CD_COORDS_TU))
+      (o.coords != CD_COORDS_XY && o.coords != CD_COORDS_TU) ||
+      (o.launch != CD_LAUNCH_GRAPH && o.launch != CD_LAUNCH_PLAIN))
     return CD_ERR_INVALID_ARG;
   const int64_t ntot = patch_ptr[n_patches];
   if (o.lbfgs_m < 0 || o.lbfgs_m > kMaxMem) return CD_ERR_INVALID_ARG;
@@ -2494,7 +2493,6 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   D.max_iter = o.max_iter;
   D.bflag = o.boundary;
   D.sigma = o.sigma > 0.0 ? o.sigma : 1.0;
-  g_trace = getenv("CD_RELAX_TRACE") != nullptr;
   D.eval_all = 0;
   D.tol = o.gtol;
   D.gtol = o.gtol;
@@ -2507,6 +2505,7 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   const RelaxSched sched = kRelaxScheds[relax_sched_index(o.precision, o.coords, n, ntot)];
   R.graph_rounds = sched.graph_rounds;
   R.wide_blocks = sched.wide_blocks;
+  R.use_graphs = o.launch == CD_LAUNCH_GRAPH;
   D.tu = o.coords == CD_COORDS_TU;
   D.tu_rmin = 1e-3 * D.sigma;
   // the Newton steps work in (x, y) and angle coordinates: none in (t, u); a
@@ -2649,7 +2648,6 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
     // hundredth of it, keeping the L-BFGS history across rounds
     const double tol32 = o.inner_tol > 0.0 ? o.inner_tol : 3e-2 / (h * h);
     const int outer_max = o.max_outer > 0 ? o.max_outer : 40;
-    const bool trace = g_trace;
     for (int outer = 0; outer < outer_max; ++outer) {
       if (rebuild) {  // a patch drifted from its halo: rebuild every patch's about its actives
         hipLaunchKernelGGL(k_patch_recentre, dim3(n_patches), dim3(256), 0, st, D, R.geom);
@@ -2674,24 +2672,6 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       const int32_t hr = hrr[0];
       rebuild = hrr[1] != 0;
       R.running = hr;
-      if (trace) {
-        std::vector<PState> hs(n_patches);
-        (void)hipMemcpy(hs.data(), D.st, sizeof(PState) * n_patches, hipMemcpyDeviceToHost);
-        double gmax = 0.0;
-        long its = 0;
-        int n32 = 0, nd = 0;
-        for (const PState& q : hs) {
-          gmax = fmax(gmax, q.gi);
-          its += q.total_it;
-          n32 += q.use32 && q.status == kRunning;
-          nd += q.status == kDone;
-        }
-        fprintf(stderr,
-                "[relax] round %d: running %d (fp32 %d) done %d, exact gi max %.3e, iterations so "
-                "far %ld, lock-step rounds last stage %d, halo rebuilds %d%s\n",
-                outer, hr, n32, nd, gmax, its, g_last_rounds, rebuilds,
-                rebuild ? " (rebuild next)" : "");
-      }
       if (hr == 0) break;
       D.ptol = ptol_ws;
       rc = run_rounds(R, st, max_rounds, true, graphs,

@@ -37,12 +37,17 @@ class RelaxOpts(ctypes.Structure):
         ("polish_stats", ctypes.c_void_p),
         ("trust_radius", ctypes.c_double),
         ("coords", ctypes.c_int32),
+        ("launch", ctypes.c_int32),
     ]
 
 # polish modes of relax_subdomains
 POLISH_DEFAULT, POLISH_NEWTON, POLISH_LBFGS = 0, 1, 2
 # coordinates of interior charges: (x, y) under the wall rule, or (t, u) of Sec. II.D
 COORDS_XY, COORDS_TU = 0, 1
+# lock-step rounds replayed from HIP graphs, or launched one by one
+LAUNCH_GRAPH, LAUNCH_PLAIN = 0, 1
+# candidates of relax_autotune
+RELAX_SCHEDULES = 9
 
 
 def _bind(L):
@@ -95,7 +100,8 @@ class RelaxResult:
 def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, gtol=1e-3,
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
                      step0=0.0, sigma=0.0, boundary=None, polish=POLISH_DEFAULT, max_polish_iter=0,
-                     newton_tol=0.0, cg_eta=0.0, trust_radius=0.0, coords=COORDS_XY) -> RelaxResult:
+                     newton_tol=0.0, cg_eta=0.0, trust_radius=0.0, coords=COORDS_XY,
+                     launch=LAUNCH_GRAPH) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
@@ -103,7 +109,8 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     border-interior split of Sec. II.B.  polish, max_polish_iter, newton_tol
     and cg_eta set the truncated-Newton polish, trust_radius (units of h) the
     mixed path's model radius (0: the library defaults); coords COORDS_TU
-    moves interior charges in the (t, u) of Sec. II.D."""
+    moves interior charges in the (t, u) of Sec. II.D; launch picks graph
+    replays or plain launches of the lock-step rounds."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -125,7 +132,7 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
                   float(inner_tol), float(halo_width), float(step0), float(sigma),
                   boundary.data_ptr() if boundary is not None else None, int(polish),
                   int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr(),
-                  float(trust_radius), int(coords))
+                  float(trust_radius), int(coords), int(launch))
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)
@@ -163,10 +170,11 @@ def relax_autotune(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, 
                                      ctypes.POINTER(RelaxOpts), _vp, ctypes.c_size_t, _vp, _vp, _vp]
         L._rtune_bound = True
     o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), 0, float(gtol), 0.0, 0.0, 0.0, float(sigma),
-                  boundary.data_ptr() if boundary is not None else None, 0, 0, 0.0, 0.0, None, 0.0, int(coords))
+                  boundary.data_ptr() if boundary is not None else None, 0, 0, 0.0, 0.0, None, 0.0, int(coords),
+                  LAUNCH_GRAPH)
     ws, nb = ops.workspace(ops.OP_RELAX, n, int(precision), dev, n_patches=P, total_active=int(ptr[-1]))
     out = (ctypes.c_int32 * 4)()
-    times = (ctypes.c_double * 9)()
+    times = (ctypes.c_double * RELAX_SCHEDULES)()
     ops.check(L.relax_autotune(x.data_ptr(), y.data_ptr(), n, P, ptr.ctypes.data, idx.data_ptr(),
                                x_start.data_ptr() if x_start is not None else None,
                                y_start.data_ptr() if y_start is not None else None, ctypes.byref(o),

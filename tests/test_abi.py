@@ -90,7 +90,8 @@ def test_relax_argument_errors_before_any_launch(L):
                     ("halo_width", ctypes.c_double), ("step0", ctypes.c_double), ("sigma", ctypes.c_double),
                     ("boundary", ctypes.c_void_p), ("polish", ctypes.c_int32), ("max_polish_iter", ctypes.c_int32),
                     ("newton_tol", ctypes.c_double), ("cg_eta", ctypes.c_double), ("polish_stats", ctypes.c_void_p),
-                    ("trust_radius", ctypes.c_double), ("coords", ctypes.c_int32)]
+                    ("trust_radius", ctypes.c_double), ("coords", ctypes.c_int32),
+                    ("launch", ctypes.c_int32)]
     vp = ctypes.c_void_p
     f = L.relax_subdomains
     f.restype = ctypes.c_int
@@ -122,6 +123,7 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(polished(cg_eta=1.0), big) == -1                        # CG target not below 1
     assert call(polished(trust_radius=-1.0), big) == -1                 # negative trust radius
     assert call(polished(coords=2), big) == -1                          # unknown coordinates
+    assert call(polished(launch=2), big) == -1                          # unknown launch mode
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0

@@ -112,7 +112,7 @@ def test_newton_from_kicked_starts(dev, prec):
 
 
 @pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
-def test_newton_graph_rounds_match_plain_launches(dev, prec, monkeypatch):
+def test_newton_graph_rounds_match_plain_launches(dev, prec):
     """Newton rounds (Hessian products, CG updates, line searches) replayed from
     captured HIP graphs equal the same kernels launched one by one, bit for
     bit, over three calls in a row."""
@@ -123,10 +123,9 @@ def test_newton_graph_rounds_match_plain_launches(dev, prec, monkeypatch):
     ptr, idx = R.build_patches(xt, yt, centres, sizes)
     fields = ("x", "y", "dE", "e_sub", "gtan_inf", "iters", "status", "polish")
     runs = []
-    for graph in ("1", "0", "1"):
-        monkeypatch.setenv("CD_RELAX_GRAPH", graph)
+    for launch in (R.LAUNCH_GRAPH, R.LAUNCH_PLAIN, R.LAUNCH_GRAPH):
         res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6,
-                                 polish=R.POLISH_NEWTON, newton_tol=ALWAYS)
+                                 polish=R.POLISH_NEWTON, newton_tol=ALWAYS, launch=launch)
         torch.cuda.synchronize()
         runs.append([getattr(res, f).clone() for f in fields])
     for a, b, c, f in zip(*runs, fields):

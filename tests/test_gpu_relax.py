@@ -253,10 +253,10 @@ def test_kicked_patches_workload5_small(dev):
 
 
 @pytest.mark.parametrize("prec", [FP64, MIXED], ids=["fp64", "mixed"])
-def test_graph_rounds_match_plain_launches(dev, prec, monkeypatch):
+def test_graph_rounds_match_plain_launches(dev, prec):
     """The rounds replayed from captured HIP graphs give the same results, bit
-    for bit, as the same kernels launched one by one (CD_RELAX_GRAPH=0), over
-    two relax calls in a row with the plain run in between."""
+    for bit, as the same kernels launched one by one (launch LAUNCH_PLAIN),
+    over two relax calls in a row with the plain run in between."""
     x, y = W.warped_lattice(3000, 0.1, 17)
     centres, _ = W.patch_draws(3000, 6, 10, 20, 18)
     sizes = np.array([1, 50, 64, 130, 300, 700], dtype=np.int32)
@@ -264,9 +264,8 @@ def test_graph_rounds_match_plain_launches(dev, prec, monkeypatch):
     ptr, idx = R.build_patches(xt, yt, centres, sizes)
     fields = ("x", "y", "dE", "e_sub", "gtan_inf", "iters", "status")
     runs = []
-    for graph in ("1", "0", "1"):
-        monkeypatch.setenv("CD_RELAX_GRAPH", graph)
-        res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
+    for launch in (R.LAUNCH_GRAPH, R.LAUNCH_PLAIN, R.LAUNCH_GRAPH):
+        res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6, launch=launch)
         torch.cuda.synchronize()
         runs.append([getattr(res, f).clone() for f in fields])
     for a, b, c, f in zip(*runs, fields):
@@ -288,7 +287,7 @@ def test_relax_autotune_then_relax(dev, prec):
     print(f"[case] relax autotune prec={prec}", flush=True)
     k, wide, rounds, pol, times = R.relax_autotune(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
     print(f"[tune] choice {k} wide {wide} rounds {rounds} polish {pol} times {np.round(times, 4)}")
-    assert 0 <= k < 9 and rounds in (4, 8, 16, 32) and pol in (-1, 1)
+    assert 0 <= k < R.RELAX_SCHEDULES and rounds in (4, 8, 16, 32) and pol in (-1, 1)
     assert all(tt > 0 for tt in times) and times[k] == min(times)
     res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
     torch.cuda.synchronize()
