@@ -2236,7 +2236,6 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
 
 // Runs rounds (eval + update) until no patch is running or max rounds.
 // Returns a CD status.
-static int g_last_rounds = 0;
 
 // Relax schedules relax_autotune chooses among (the first is the default):
 // the running-block count below which model blocks take 16 waves, lock-step
@@ -2289,6 +2288,9 @@ struct RoundGraphs {
   hipEvent_t ev = nullptr;
   hipGraphExec_t ex[2] = {nullptr, nullptr};
   bool ok = false;
+  bool broken = false;        // a capture failed: plain launches from then on
+  int32_t* hc = nullptr;      // pinned host copies of the running count, one per block in flight
+  hipEvent_t cev[2] = {nullptr, nullptr};
   bool begin(hipStream_t st) {
     if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
     if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
@@ -2303,6 +2305,16 @@ struct RoundGraphs {
       return CD_ERR_HIP;
     return CD_OK;
   }
+  bool counts() {  // the pinned count slots and their events, made on first use
+    if (!hc && hipHostMalloc(reinterpret_cast<void**>(&hc), 2 * sizeof(int32_t),
+                             hipHostMallocDefault) != hipSuccess) {
+      hc = nullptr;
+      return false;
+    }
+    for (hipEvent_t& e : cev)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+    return true;
+  }
   ~RoundGraphs() {
     for (hipGraphExec_t& x : ex)
       if (x) (void)hipGraphExecDestroy(x);
@@ -2311,6 +2323,12 @@ struct RoundGraphs {
       (void)hipStreamSynchronize(cs);
       (void)hipStreamDestroy(cs);
     }
+    for (hipEvent_t& e : cev)
+      if (e) {
+        (void)hipEventSynchronize(e);  // the copy into hc it follows has landed
+        (void)hipEventDestroy(e);
+      }
+    if (hc) (void)hipHostFree(hc);
   }
 };
 
@@ -2337,66 +2355,72 @@ static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn
 
 // eval(stream, shape) enqueues one evaluation; shape(): 0 or 1, the
 // evaluation's launch shape for the current running count.
+//
+// The rounds go in blocks of graph_rounds (one graph replay, or the same
+// kernels launched one by one), each followed by an asynchronous copy of the
+// running count into pinned host memory.  Two blocks are kept in flight: the
+// host waits for the count of block k - 1 only once block k is queued, so the
+// device does not idle while the host reads it.  The launch shape of block k
+// comes from the count after block k - 2 (the last one read), the same on
+// both launch modes, so their results agree bit for bit; blocks queued after
+// the count reached zero find no running patch and change nothing.
 template <class EvalFn, class ShapeFn>
 static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, RoundGraphs& G,
                       EvalFn eval, ShapeFn shape) {
   RelaxDev& D = R.D;
-  int32_t h_running = 0;
   const int gr = R.graph_rounds;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
-  int r0 = 0;  // first round of the plain launches
-  if (R.use_graphs && G.begin(st)) {
-    hipStream_t cs = G.cs;
-    bool fallback = false;
-    int r = 0;
-    for (; r < max_rounds; r += gr) {
+  if (!G.counts()) return CD_ERR_HIP;
+  const bool graphs = R.use_graphs && G.begin(st);
+  hipStream_t ls = graphs ? G.cs : st;  // the stream the blocks go to
+  int launched = 0, read = 0;           // blocks queued; blocks whose count was read
+  bool stop = false;
+  for (int r = 0;;) {
+    if (!stop && r < max_rounds && launched - read < 2) {
       const int sh = shape();
-      if (!G.ex[sh]) {
-        // capture this shape's rounds; a capture or instantiation that fails
+      if (graphs && !G.broken && !G.ex[sh]) {
+        // capture this shape's block; a capture or instantiation that fails
         // leaves nothing enqueued and hands the rounds to plain launches
         hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-          fallback = true;
-          break;
+        if (hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          G.broken = true;
+        } else {
+          for (int q = 0; q < gr; ++q) launch_round(R, ls, hist32, sh, eval);
+          const hipError_t ce = hipStreamEndCapture(ls, &g);
+          const hipError_t ie =
+              (ce == hipSuccess && g) ? hipGraphInstantiate(&G.ex[sh], g, nullptr, nullptr, 0)
+                                      : hipErrorUnknown;
+          if (g) (void)hipGraphDestroy(g);
+          if (ie != hipSuccess) {
+            G.ex[sh] = nullptr;
+            G.broken = true;
+          }
         }
-        for (int q = 0; q < gr; ++q) launch_round(R, cs, hist32, sh, eval);
-        const hipError_t ce = hipStreamEndCapture(cs, &g);
-        const hipError_t ie =
-            (ce == hipSuccess && g) ? hipGraphInstantiate(&G.ex[sh], g, nullptr, nullptr, 0)
-                                    : hipErrorUnknown;
-        if (g) (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) {
-          G.ex[sh] = nullptr;
-          (void)hipGetLastError();  // the failed capture's error is handled here
-          fallback = true;
-          break;
-        }
+        (void)hipGetLastError();  // a failed capture's error is handled here
       }
-      g_last_rounds = r + gr;
-      if (hipGraphLaunch(G.ex[sh], cs) != hipSuccess ||
-          hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, cs) !=
+      if (graphs && !G.broken) {
+        if (hipGraphLaunch(G.ex[sh], ls) != hipSuccess) return CD_ERR_HIP;
+      } else {
+        for (int q = 0; q < gr; ++q) launch_round(R, ls, hist32, sh, eval);
+      }
+      const int b = launched & 1;
+      if (hipMemcpyAsync(G.hc + b, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, ls) !=
               hipSuccess ||
-          hipStreamSynchronize(cs) != hipSuccess)
+          hipEventRecord(G.cev[b], ls) != hipSuccess)
         return CD_ERR_HIP;
-      R.running = h_running;
-      if (h_running <= 0) break;
+      ++launched;
+      r += gr;
+      continue;
     }
-    const int rc = G.end(st);
-    if (rc || !fallback) return rc;
-    r0 = r;
+    if (read == launched) break;  // nothing in flight and nothing more to queue
+    const int b = read & 1;
+    if (hipEventSynchronize(G.cev[b]) != hipSuccess) return CD_ERR_HIP;
+    R.running = G.hc[b];
+    ++read;
+    if (R.running <= 0) stop = true;
   }
-  for (int r = r0; r < max_rounds; ++r) {
-    g_last_rounds = r + 1;
-    launch_round(R, st, hist32, shape(), eval);
-    if ((r + 1) % gr == 0) {
-      if (hipMemcpyAsync(&h_running, D.running, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
-          hipSuccess)
-        return CD_ERR_HIP;
-      if (hipStreamSynchronize(st) != hipSuccess) return CD_ERR_HIP;
-      R.running = h_running;
-      if (h_running <= 0) break;
-    }
-  }
+  const int rc = graphs ? G.end(st) : CD_OK;
+  if (rc) return rc;
   return hip_status(hipGetLastError());
 }
 
