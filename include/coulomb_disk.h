@@ -233,10 +233,19 @@ typedef struct {
                                 either way.  No Newton polish in (t, u) (L-BFGS only). */
   int32_t launch;            /* CD_LAUNCH_GRAPH: lock-step rounds replayed from HIP graphs;
                                 CD_LAUNCH_PLAIN: the same kernels launched one by one */
+  int32_t exterior_model;    /* CD_EXTERIOR_DEFAULT: set by precision (CD_FP64 exact
+                                evaluations, CD_MIXED the model); CD_EXTERIOR_EXACT: every
+                                gradient an exact FP64 evaluation over all n (CD_FP64 only;
+                                with CD_MIXED the call returns CD_ERR_INVALID_ARG);
+                                CD_EXTERIOR_MODEL: the model of CD_MIXED (explicit active and
+                                halo pairs plus the exactly re-expanded far field); with
+                                CD_FP64 its pairs are FP64 throughout, and the workspace is
+                                that of CD_MIXED */
 } cd_relax_opts;
 
 enum { CD_COORDS_XY = 0, CD_COORDS_TU = 1 };
 enum { CD_LAUNCH_GRAPH = 0, CD_LAUNCH_PLAIN = 1 };
+enum { CD_EXTERIOR_DEFAULT = 0, CD_EXTERIOR_EXACT = 1, CD_EXTERIOR_MODEL = 2 };
 
 enum { CD_POLISH_DEFAULT = 0, CD_POLISH_NEWTON = 1, CD_POLISH_LBFGS = 2 };
 

@@ -2484,7 +2484,16 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
   for (int p = 0; p < n_patches; ++p)
     if (patch_ptr[p + 1] <= patch_ptr[p] || patch_ptr[p + 1] - patch_ptr[p] > n)
       return CD_ERR_INVALID_ARG;
-  const cd_relax_opts o = *opts;
+  cd_relax_opts o = *opts;
+  if (o.exterior_model < CD_EXTERIOR_DEFAULT || o.exterior_model > CD_EXTERIOR_MODEL ||
+      (o.exterior_model == CD_EXTERIOR_EXACT && o.precision != CD_FP64))
+    return CD_ERR_INVALID_ARG;
+  if (o.exterior_model == CD_EXTERIOR_MODEL && o.precision == CD_FP64) {
+    // the model with FP64 pairs throughout: the mixed path, never below its
+    // FP64 switch
+    o.precision = CD_MIXED;
+    o.inner_tol = 1e300;
+  }
   if (!(o.gtol > 0.0) || o.max_iter < 0 || o.halo_width < 0.0 || o.inner_tol < 0.0 ||
       o.step0 < 0.0 || o.max_outer < 0 || !(o.sigma >= 0.0 && o.sigma <= 1.0))
     return CD_ERR_INVALID_ARG;

@@ -38,6 +38,7 @@ class RelaxOpts(ctypes.Structure):
         ("trust_radius", ctypes.c_double),
         ("coords", ctypes.c_int32),
         ("launch", ctypes.c_int32),
+        ("exterior_model", ctypes.c_int32),
     ]
 
 # polish modes of relax_subdomains
@@ -46,6 +47,8 @@ POLISH_DEFAULT, POLISH_NEWTON, POLISH_LBFGS = 0, 1, 2
 COORDS_XY, COORDS_TU = 0, 1
 # lock-step rounds replayed from HIP graphs, or launched one by one
 LAUNCH_GRAPH, LAUNCH_PLAIN = 0, 1
+# exterior of the relax: set by precision, exact FP64 evaluations, or the halo + far-field model
+EXTERIOR_DEFAULT, EXTERIOR_EXACT, EXTERIOR_MODEL = 0, 1, 2
 # candidates of relax_autotune
 RELAX_SCHEDULES = 9
 
@@ -101,7 +104,7 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
                      max_iter=None, lbfgs_m=16, max_outer=0, inner_tol=0.0, halo_width=0.0,
                      step0=0.0, sigma=0.0, boundary=None, polish=POLISH_DEFAULT, max_polish_iter=0,
                      newton_tol=0.0, cg_eta=0.0, trust_radius=0.0, coords=COORDS_XY,
-                     launch=LAUNCH_GRAPH) -> RelaxResult:
+                     launch=LAUNCH_GRAPH, exterior_model=EXTERIOR_DEFAULT) -> RelaxResult:
     """Relax every patch against the frozen snapshot (x, y); see coulomb_disk.h.
 
     max_iter defaults to 300 per round for the mixed path and 8000 in total for
@@ -110,7 +113,8 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     and cg_eta set the truncated-Newton polish, trust_radius (units of h) the
     mixed path's model radius (0: the library defaults); coords COORDS_TU
     moves interior charges in the (t, u) of Sec. II.D; launch picks graph
-    replays or plain launches of the lock-step rounds."""
+    replays or plain launches of the lock-step rounds; exterior_model
+    EXTERIOR_MODEL with FP64 runs the model with FP64 pairs throughout."""
     if max_iter is None:
         max_iter = 300 if precision == MIXED else 8000
     dev = ops._chk(x, y)
@@ -132,7 +136,7 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
                   float(inner_tol), float(halo_width), float(step0), float(sigma),
                   boundary.data_ptr() if boundary is not None else None, int(polish),
                   int(max_polish_iter), float(newton_tol), float(cg_eta), pst.data_ptr(),
-                  float(trust_radius), int(coords), int(launch))
+                  float(trust_radius), int(coords), int(launch), int(exterior_model))
     f = dict(dtype=torch.float64, device=dev)
     xo = torch.empty(ntot, **f)
     yo = torch.empty(ntot, **f)
@@ -141,7 +145,8 @@ def relax_subdomains(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED
     gt = torch.empty(P, **f)
     it = torch.empty((P, 2), dtype=torch.int32, device=dev)
     stt = torch.empty(P, dtype=torch.int32, device=dev)
-    ws, nb = ops.workspace(ops.OP_RELAX, n, int(precision), dev, n_patches=P, total_active=ntot)
+    ws_prec = MIXED if exterior_model == EXTERIOR_MODEL else int(precision)
+    ws, nb = ops.workspace(ops.OP_RELAX, n, ws_prec, dev, n_patches=P, total_active=ntot)
     ops.check(ops.lib().relax_subdomains(
         x.data_ptr(), y.data_ptr(), n, P, ptr.ctypes.data, idx.data_ptr(),
         x_start.data_ptr() if x_start is not None else None,
@@ -171,7 +176,7 @@ def relax_autotune(x, y, ptr, idx, x_start=None, y_start=None, precision=MIXED, 
         L._rtune_bound = True
     o = RelaxOpts(int(precision), int(max_iter), int(lbfgs_m), 0, float(gtol), 0.0, 0.0, 0.0, float(sigma),
                   boundary.data_ptr() if boundary is not None else None, 0, 0, 0.0, 0.0, None, 0.0, int(coords),
-                  LAUNCH_GRAPH)
+                  LAUNCH_GRAPH, EXTERIOR_DEFAULT)
     ws, nb = ops.workspace(ops.OP_RELAX, n, int(precision), dev, n_patches=P, total_active=int(ptr[-1]))
     out = (ctypes.c_int32 * 4)()
     times = (ctypes.c_double * RELAX_SCHEDULES)()

@@ -91,7 +91,7 @@ def test_relax_argument_errors_before_any_launch(L):
                     ("boundary", ctypes.c_void_p), ("polish", ctypes.c_int32), ("max_polish_iter", ctypes.c_int32),
                     ("newton_tol", ctypes.c_double), ("cg_eta", ctypes.c_double), ("polish_stats", ctypes.c_void_p),
                     ("trust_radius", ctypes.c_double), ("coords", ctypes.c_int32),
-                    ("launch", ctypes.c_int32)]
+                    ("launch", ctypes.c_int32), ("exterior_model", ctypes.c_int32)]
     vp = ctypes.c_void_p
     f = L.relax_subdomains
     f.restype = ctypes.c_int
@@ -124,6 +124,8 @@ def test_relax_argument_errors_before_any_launch(L):
     assert call(polished(trust_radius=-1.0), big) == -1                 # negative trust radius
     assert call(polished(coords=2), big) == -1                          # unknown coordinates
     assert call(polished(launch=2), big) == -1                          # unknown launch mode
+    assert call(polished(exterior_model=3), big) == -1                  # unknown exterior model
+    assert call(polished(precision=1, exterior_model=1), big) == -1     # exact exterior needs FP64
     assert call(o, 1024) == -2                                          # workspace too small
     assert call(o, big, np.array([0, 10, 10], dtype=np.int32)) == -1    # empty patch
     assert call(o, big, np.array([1, 10, 30], dtype=np.int32)) == -1    # offsets must start at 0

@@ -292,3 +292,26 @@ def test_relax_autotune_then_relax(dev, prec):
     res = R.relax_subdomains(xt, yt, ptr, idx, precision=prec, gtol=1e-6)
     torch.cuda.synchronize()
     check_endpoints(x, y, ptr, idx.cpu().numpy(), res, 1e-6, f"tuned-{prec}")
+
+
+def test_exterior_model_option(dev):
+    """The exterior option of the relax: the model with FP64 pairs throughout
+    (EXTERIOR_MODEL on the FP64 path) is the mixed path kept above its FP64
+    switch, bit for bit, and passes the oracle's endpoint checks; EXTERIOR_EXACT
+    on the FP64 path is the plain path's default, bit for bit."""
+    x, y = W.warped_lattice(3000, 0.1, 7)
+    centres, _ = W.patch_draws(3000, 6, 10, 20, 8)
+    sizes = np.array([1, 37, 64, 65, 200, 400], dtype=np.int32)
+    xt, yt = t(x, dev), t(y, dev)
+    ptr, idx = R.build_patches(xt, yt, centres, sizes)
+    fields = ("x", "y", "dE", "e_sub", "gtan_inf", "iters", "status")
+    print("[case] exterior model option", flush=True)
+    a = R.relax_subdomains(xt, yt, ptr, idx, precision=FP64, gtol=1e-6, exterior_model=R.EXTERIOR_MODEL)
+    b = R.relax_subdomains(xt, yt, ptr, idx, precision=MIXED, gtol=1e-6, inner_tol=1e300)
+    c = R.relax_subdomains(xt, yt, ptr, idx, precision=FP64, gtol=1e-6, exterior_model=R.EXTERIOR_EXACT)
+    d = R.relax_subdomains(xt, yt, ptr, idx, precision=FP64, gtol=1e-6)
+    torch.cuda.synchronize()
+    for f in fields:
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+        assert torch.equal(getattr(c, f), getattr(d, f)), f
+    check_endpoints(x, y, ptr, idx.cpu().numpy(), a, 1e-6, "exterior-model-fp64")
