@@ -2316,13 +2316,11 @@ struct RoundGraphs {
     return true;
   }
   ~RoundGraphs() {
+    if (cs) (void)hipStreamSynchronize(cs);  // no replay is still running below
     for (hipGraphExec_t& x : ex)
       if (x) (void)hipGraphExecDestroy(x);
     if (ev) (void)hipEventDestroy(ev);
-    if (cs) {
-      (void)hipStreamSynchronize(cs);
-      (void)hipStreamDestroy(cs);
-    }
+    if (cs) (void)hipStreamDestroy(cs);
     for (hipEvent_t& e : cev)
       if (e) {
         (void)hipEventSynchronize(e);  // the copy into hc it follows has landed
