@@ -93,3 +93,10 @@ def test_voronoi_degenerate_inputs(dev):
         z, psi = ST.voronoi(torch.tensor(x, device=dev), torch.tensor(y, device=dev))
         assert z.cpu().numpy().tolist() == want
         assert np.all(psi.cpu().numpy() == 0.0)
+        # no bounded cell: fractions and the mean are 0, the counts exact
+        st = ST.stats(z, psi)
+        assert st["bounded_cells"] == 0 and st["mean_abs_psi6"] == 0.0
+        assert all(v == 0.0 for v in st["P_z"].values())
+        assert st["hull"] == want.count(-2) and st["unresolved"] == want.count(-1)
+        st0 = ST.stats(z)  # without psi_6
+        assert st0["hull"] == st["hull"] and st0["mean_abs_psi6"] == 0.0

@@ -72,6 +72,23 @@ def test_noalloc_matches_forces_two_calls(dev, prec):
             assert abs(E - oE) <= etol * oE
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_noalloc_smallest_sizes(dev, prec):
+    # one charge (no pair: zero force and energy), two, and one ragged block
+    for n in (1, 2, 65):
+        x, y = W.uniform_disk(n, 2000 + n)
+        xt = torch.tensor(x, device=dev)
+        yt = torch.tensor(y, device=dev)
+        fx, fy, E = _call(xt, yt, prec)
+        if n == 1:
+            assert fx[0] == 0.0 and fy[0] == 0.0 and E == 0.0
+            continue
+        ox, oy = O.forces(x, y)
+        oE = O.energy(x, y)
+        ftol, etol = (1e-11, 1e-13) if prec == FP64 else (1e-5, 1e-7)
+        assert _rel_rms(fx, fy, ox, oy) <= ftol and abs(E - oE) <= etol * oE
+
+
 def test_noalloc_refuses_sizes_beyond_scratch(dev):
     x = torch.zeros(1, dtype=torch.float64, device=dev)
     rc = _noalloc()(x.data_ptr(), x.data_ptr(), 706305, MIXED, x.data_ptr(), x.data_ptr(), None,
