@@ -38,6 +38,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -48,6 +49,11 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
                              int precision);
 
 constexpr int kMaxMem = 16;  // largest L-BFGS memory; the workspace is sized for it
+// plain path: the exact evaluations take the Hessian blocks every kBlockEvery-th
+// iteration, and at every one once the reduced gradient is within kBlockNear
+// times the Newton switch
+constexpr int kBlockEvery = 4;
+constexpr double kBlockNear = 2.0;
 
 // ------------------------------------------------------ patch construction --
 __device__ __forceinline__ double dist2_rn(double ax, double ay, double bx, double by) {
@@ -174,6 +180,7 @@ struct PState {
   double eta;        // relative CG target of the last Newton step
   double gexact;     // mixed path: the exact reduced gradient at the last round's check
   int force64;       // mixed path: FP64 model pairs from here on (FP32 rounds stalled)
+  int skip_k;        // plain path: the next exact evaluation leaves out the Hessian blocks
   int pad2;
 };
 
@@ -523,6 +530,9 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   const int p = bk.x;
   if (MODE == kGrad && !R.eval_all && (R.st[p].status != kRunning || R.st[p].phase == kPhaseCG))
     return;
+  // kGrad takes the Hessian blocks unless the patch's update said it can do
+  // without them this time (plain path, between Newton phases); uniform per wave
+  const bool wk = MODE == kFar || (MODE == kGrad && (R.eval_all || !R.st[p].skip_k));
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int a = bk.y + lane;
   const bool ok = a < a1;
@@ -533,87 +543,98 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   const uint64_t* mask = (MODE == kFar ? R.maskAH : R.maskA) + (size_t)p * R.nbN;
   double G0 = 0.0, G1 = 0.0, G2 = 0.0, G3 = 0.0, G4 = 0.0, Ee = 0.0, Ec = 0.0;
   const int J0 = blockIdx.y * R.jb, J1 = min(R.nbN, J0 + R.jb);
-  for (int J = J0; J < J1; ++J) {
-    const uint64_t m = mask[J];  // wave-uniform: charges of the patch (and halo) are skipped
-    const int jn = min(64, R.n - J * 64);
-    const double* xb = R.x + (size_t)J * 64;
-    const double* yb = R.y + (size_t)J * 64;
-    double eb = 0.0;
+  auto pairs = [&](auto wk_tag) {
+    constexpr bool WK = decltype(wk_tag)::value;
+    for (int J = J0; J < J1; ++J) {
+      const uint64_t m = mask[J];  // wave-uniform: charges of the patch (and halo) are skipped
+      const int jn = min(64, R.n - J * 64);
+      const double* xb = R.x + (size_t)J * 64;
+      const double* yb = R.y + (size_t)J * 64;
+      double eb = 0.0;
 #pragma unroll 8
-    for (int jj = 0; jj < jn; ++jj) {
-      const bool skip = (m >> jj) & 1ull;
-      const double xj = xb[jj], yj = yb[jj];
-      const double dx = xi - xj, dy = yi - yj;
-      const double r2 = __builtin_fma(dx, dx, dy * dy);
-      if (MODE == kDelta) {
-        const double ox = xo - xj, oy = yo - yj;
-        const double ro2 = __builtin_fma(ox, ox, oy * oy);
-        const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
-        const double rn = r2 * ri, ro = ro2 * roi;
-        const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
-        const double v = num * ri * roi / (rn + ro);
-        eb += skip ? 0.0 : v;
-      } else {
-        double inv = rsqrt64(r2);
-        inv = skip ? 0.0 : inv;
-        const double i3 = inv * inv * inv;
-        G0 = __builtin_fma(-dx, i3, G0);
-        G1 = __builtin_fma(-dy, i3, G1);
-        if (MODE == kGrad) eb += inv;
-        const double i5 = i3 * inv * inv;
-        const double t3 = 3.0 * i5;
-        G2 += __builtin_fma(t3 * dx, dx, -i3);
-        G3 += t3 * dx * dy;
-        G4 += __builtin_fma(t3 * dy, dy, -i3);
-      }
-    }
-    const double tt = Ee + eb;  // Neumaier across 64-charge blocks
-    Ec += fabs(Ee) >= fabs(eb) ? (Ee - tt) + eb : (eb - tt) + Ee;
-    Ee = tt;
-  }
-  if (MODE != kFar && blockIdx.y == 0) {
-    // active-active pairs at the trial positions (half weight in the energy)
-#pragma unroll 4
-    for (int b = a0; b < a1; ++b) {
-      const double xj = R.tx[b], yj = R.ty[b];
-      const double dx = xi - xj, dy = yi - yj;
-      const double r2 = __builtin_fma(dx, dx, dy * dy);
-      if (MODE == kDelta) {
-        const double ox = xo - R.z0x[b], oy = yo - R.z0y[b];
-        const double ro2 = __builtin_fma(ox, ox, oy * oy);
-        double v = 0.0;
-        if (b != ac) {
+      for (int jj = 0; jj < jn; ++jj) {
+        const bool skip = (m >> jj) & 1ull;
+        const double xj = xb[jj], yj = yb[jj];
+        const double dx = xi - xj, dy = yi - yj;
+        const double r2 = __builtin_fma(dx, dx, dy * dy);
+        if (MODE == kDelta) {
+          const double ox = xo - xj, oy = yo - yj;
+          const double ro2 = __builtin_fma(ox, ox, oy * oy);
           const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
           const double rn = r2 * ri, ro = ro2 * roi;
           const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
-          v = 0.5 * (num * ri * roi / (rn + ro));
+          const double v = num * ri * roi / (rn + ro);
+          eb += skip ? 0.0 : v;
+        } else {
+          double inv = rsqrt64(r2);
+          inv = skip ? 0.0 : inv;
+          const double i3 = inv * inv * inv;
+          G0 = __builtin_fma(-dx, i3, G0);
+          G1 = __builtin_fma(-dy, i3, G1);
+          if (MODE == kGrad) eb += inv;
+          if (WK) {
+            const double i5 = i3 * inv * inv;
+            const double t3 = 3.0 * i5;
+            G2 += __builtin_fma(t3 * dx, dx, -i3);
+            G3 += t3 * dx * dy;
+            G4 += __builtin_fma(t3 * dy, dy, -i3);
+          }
         }
-        const double tt = Ee + v;
-        Ec += fabs(Ee) >= fabs(v) ? (Ee - tt) + v : (v - tt) + Ee;
-        Ee = tt;
-      } else {
-        double inv = rsqrt64(r2);
-        inv = (b == ac) ? 0.0 : inv;
-        const double i3 = inv * inv * inv;
-        const double h = 0.5 * inv;
-        const double tt = Ee + h;
-        Ec += fabs(Ee) >= fabs(h) ? (Ee - tt) + h : (h - tt) + Ee;
-        Ee = tt;
-        G0 = __builtin_fma(-dx, i3, G0);
-        G1 = __builtin_fma(-dy, i3, G1);
-        const double t3 = 3.0 * i3 * inv * inv;
-        G2 += __builtin_fma(t3 * dx, dx, -i3);
-        G3 += t3 * dx * dy;
-        G4 += __builtin_fma(t3 * dy, dy, -i3);
+      }
+      const double tt = Ee + eb;  // Neumaier across 64-charge blocks
+      Ec += fabs(Ee) >= fabs(eb) ? (Ee - tt) + eb : (eb - tt) + Ee;
+      Ee = tt;
+    }
+    if (MODE != kFar && blockIdx.y == 0) {
+      // active-active pairs at the trial positions (half weight in the energy)
+#pragma unroll 4
+      for (int b = a0; b < a1; ++b) {
+        const double xj = R.tx[b], yj = R.ty[b];
+        const double dx = xi - xj, dy = yi - yj;
+        const double r2 = __builtin_fma(dx, dx, dy * dy);
+        if (MODE == kDelta) {
+          const double ox = xo - R.z0x[b], oy = yo - R.z0y[b];
+          const double ro2 = __builtin_fma(ox, ox, oy * oy);
+          double v = 0.0;
+          if (b != ac) {
+            const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
+            const double rn = r2 * ri, ro = ro2 * roi;
+            const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
+            v = 0.5 * (num * ri * roi / (rn + ro));
+          }
+          const double tt = Ee + v;
+          Ec += fabs(Ee) >= fabs(v) ? (Ee - tt) + v : (v - tt) + Ee;
+          Ee = tt;
+        } else {
+          double inv = rsqrt64(r2);
+          inv = (b == ac) ? 0.0 : inv;
+          const double i3 = inv * inv * inv;
+          const double h = 0.5 * inv;
+          const double tt = Ee + h;
+          Ec += fabs(Ee) >= fabs(h) ? (Ee - tt) + h : (h - tt) + Ee;
+          Ee = tt;
+          G0 = __builtin_fma(-dx, i3, G0);
+          G1 = __builtin_fma(-dy, i3, G1);
+          if (WK) {
+            const double t3 = 3.0 * i3 * inv * inv;
+            G2 += __builtin_fma(t3 * dx, dx, -i3);
+            G3 += t3 * dx * dy;
+            G4 += __builtin_fma(t3 * dy, dy, -i3);
+          }
+        }
       }
     }
-  }
+  };
+  if (MODE == kDelta || !wk)
+    pairs(std::false_type{});
+  else
+    pairs(std::true_type{});
   if (!ok) return;
   const size_t q = (size_t)blockIdx.y * R.ntot + a;
   R.px[q] = G0;
   R.py[q] = G1;
   if (MODE != kFar) R.pe[q] = Ee + Ec;
-  if (MODE != kDelta) {
+  if (MODE != kDelta && wk) {
     R.pkxx[q] = G2;
     R.pkxy[q] = G3;
     R.pkyy[q] = G4;
@@ -638,6 +659,8 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a = blockIdx.x * 64 + lane;
   const bool ok = a < R.ntot;
+  // the Hessian blocks were taken for this active's patch (see k_exact)
+  const bool wk = ok && (mode == kFar || (mode == kGrad && (R.eval_all || !R.st[R.pid[a]].skip_k)));
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (ok) {
     for (int sp = w; sp < R.splits; sp += kESW) {
@@ -645,7 +668,7 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
       v[0] += R.px[q];
       v[1] += R.py[q];
       if (mode != kFar) v[2] += R.pe[q];
-      if (grad) {
+      if (wk) {
         v[3] += R.pkxx[q];
         v[4] += R.pkxy[q];
         v[5] += R.pkyy[q];
@@ -673,9 +696,11 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
   if (grad) {
     R.hgx[a] = v[0];
     R.hgy[a] = v[1];
-    R.hkxx[a] = v[3];
-    R.hkxy[a] = v[4];
-    R.hkyy[a] = v[5];
+    if (wk) {  // else the last blocks taken stay (the preconditioner may lag)
+      R.hkxx[a] = v[3];
+      R.hkxy[a] = v[4];
+      R.hkyy[a] = v[5];
+    }
   }
   R.eterm[a] = v[2];
 }
@@ -1399,6 +1424,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   }
   s.evals++;
   const bool was_init = s.init;
+  const bool k_fresh = !s.skip_k;  // this evaluation took the Hessian blocks
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int m = R.m;
   double* rho = R.rho + (size_t)p * m;
@@ -1612,7 +1638,16 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     }
     // truncated-Newton polish: the plain path enters Newton mode below
     // newton_tol (the mixed path's round check decides there)
-    if (R.polish && !R.fgx && !s.newton_off && gi <= R.newton_tol) s.newton = 1;
+    // (the Newton product needs the exact blocks at z: with stale ones the
+    // patch takes one more L-BFGS step and enters with fresh ones)
+    if (R.polish && !R.fgx && !s.newton_off && gi <= R.newton_tol && k_fresh) s.newton = 1;
+    if (!R.fgx) {
+      // the plain path takes each active's Hessian block (the preconditioner)
+      // every kBlockEvery-th iteration, from close to the Newton switch on,
+      // and in Newton mode, where the product needs it at every point
+      const bool near_newton = R.polish && !s.newton_off && gi <= kBlockNear * R.newton_tol;
+      s.skip_k = !(s.newton || near_newton || s.it % kBlockEvery == 0);
+    }
     if (s.newton) {
       if (R.fgx && !was_init) {
         // mixed path: one Newton step per expansion of the far field; the
