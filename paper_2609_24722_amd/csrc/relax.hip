@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   const double yi = R.ty[ac];
   const double xo = R.z0x[ac], yo = R.z0y[ac];  // snapshot position (kDelta)
   const uint64_t* mask = (MODE == kFar ? R.maskAH : R.maskA) + (size_t)p * R.nbN;
-  double G0 = 0.0, G1 = 0.0, G2 = 0.0, G3 = 0.0, G4 = 0.0, Ee = 0.0, Ec = 0.0;
+  double G0 = 0.0, G1 = 0.0, G2 = 0.0, G3 = 0.0, G4 = 0.0, S3 = 0.0, Ee = 0.0, Ec = 0.0;
   const int J0 = blockIdx.y * R.jb, J1 = min(R.nbN, J0 + R.jb);
   auto pairs = [&](auto wk_tag) {
     constexpr bool WK = decltype(wk_tag)::value;
@@ -573,11 +573,14 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
           G1 = __builtin_fma(-dy, i3, G1);
           if (MODE == kGrad) eb += inv;
           if (WK) {
-            const double i5 = i3 * inv * inv;
-            const double t3 = 3.0 * i5;
-            G2 += __builtin_fma(t3 * dx, dx, -i3);
-            G3 += t3 * dx * dy;
-            G4 += __builtin_fma(t3 * dy, dy, -i3);
+            // K = 3 d d^T / r^5 - I / r^3: the d d^T part here, the sum of
+            // 1/r^3 (the same for both diagonal entries) apart in S3
+            const double t3 = 3.0 * i3 * (inv * inv);
+            const double u = t3 * dx;
+            G2 = __builtin_fma(u, dx, G2);
+            G3 = __builtin_fma(u, dy, G3);
+            G4 = __builtin_fma(t3 * dy, dy, G4);
+            S3 += i3;
           }
         }
       }
@@ -616,10 +619,12 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
           G0 = __builtin_fma(-dx, i3, G0);
           G1 = __builtin_fma(-dy, i3, G1);
           if (WK) {
-            const double t3 = 3.0 * i3 * inv * inv;
-            G2 += __builtin_fma(t3 * dx, dx, -i3);
-            G3 += t3 * dx * dy;
-            G4 += __builtin_fma(t3 * dy, dy, -i3);
+            const double t3 = 3.0 * i3 * (inv * inv);
+            const double u = t3 * dx;
+            G2 = __builtin_fma(u, dx, G2);
+            G3 = __builtin_fma(u, dy, G3);
+            G4 = __builtin_fma(t3 * dy, dy, G4);
+            S3 += i3;
           }
         }
       }
@@ -635,9 +640,9 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   R.py[q] = G1;
   if (MODE != kFar) R.pe[q] = Ee + Ec;
   if (MODE != kDelta && wk) {
-    R.pkxx[q] = G2;
+    R.pkxx[q] = G2 - S3;
     R.pkxy[q] = G3;
-    R.pkyy[q] = G4;
+    R.pkyy[q] = G4 - S3;
   }
   if (MODE == kFar && blockIdx.y == 0) {
     R.zrx[a] = xi;  // the expansion point
