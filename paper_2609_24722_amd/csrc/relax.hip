@@ -551,39 +551,48 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
       const double* xb = R.x + (size_t)J * 64;
       const double* yb = R.y + (size_t)J * 64;
       double eb = 0.0;
+      // the skip test only in blocks that hold charges of the patch (or its
+      // halo); most blocks of a large N hold none
+      auto block = [&](auto masked_tag) {
+        constexpr bool M = decltype(masked_tag)::value;
 #pragma unroll 8
-      for (int jj = 0; jj < jn; ++jj) {
-        const bool skip = (m >> jj) & 1ull;
-        const double xj = xb[jj], yj = yb[jj];
-        const double dx = xi - xj, dy = yi - yj;
-        const double r2 = __builtin_fma(dx, dx, dy * dy);
-        if (MODE == kDelta) {
-          const double ox = xo - xj, oy = yo - yj;
-          const double ro2 = __builtin_fma(ox, ox, oy * oy);
-          const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
-          const double rn = r2 * ri, ro = ro2 * roi;
-          const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
-          const double v = num * ri * roi / (rn + ro);
-          eb += skip ? 0.0 : v;
-        } else {
-          double inv = rsqrt64(r2);
-          inv = skip ? 0.0 : inv;
-          const double i3 = inv * inv * inv;
-          G0 = __builtin_fma(-dx, i3, G0);
-          G1 = __builtin_fma(-dy, i3, G1);
-          if (MODE == kGrad) eb += inv;
-          if (WK) {
-            // K = 3 d d^T / r^5 - I / r^3: the d d^T part here, the sum of
-            // 1/r^3 (the same for both diagonal entries) apart in S3
-            const double t3 = 3.0 * i3 * (inv * inv);
-            const double u = t3 * dx;
-            G2 = __builtin_fma(u, dx, G2);
-            G3 = __builtin_fma(u, dy, G3);
-            G4 = __builtin_fma(t3 * dy, dy, G4);
-            S3 += i3;
+        for (int jj = 0; jj < jn; ++jj) {
+          const bool skip = M && ((m >> jj) & 1ull);
+          const double xj = xb[jj], yj = yb[jj];
+          const double dx = xi - xj, dy = yi - yj;
+          const double r2 = __builtin_fma(dx, dx, dy * dy);
+          if (MODE == kDelta) {
+            const double ox = xo - xj, oy = yo - yj;
+            const double ro2 = __builtin_fma(ox, ox, oy * oy);
+            const double ri = rsqrt64(r2), roi = rsqrt64(ro2);
+            const double rn = r2 * ri, ro = ro2 * roi;
+            const double num = (ox - dx) * (ox + dx) + (oy - dy) * (oy + dy);
+            const double v = num * ri * roi / (rn + ro);
+            eb += skip ? 0.0 : v;
+          } else {
+            double inv = rsqrt64(r2);
+            inv = skip ? 0.0 : inv;
+            const double i3 = inv * inv * inv;
+            G0 = __builtin_fma(-dx, i3, G0);
+            G1 = __builtin_fma(-dy, i3, G1);
+            if (MODE == kGrad) eb += inv;
+            if (WK) {
+              // K = 3 d d^T / r^5 - I / r^3: the d d^T part here, the sum of
+              // 1/r^3 (the same for both diagonal entries) apart in S3
+              const double t3 = 3.0 * i3 * (inv * inv);
+              const double u = t3 * dx;
+              G2 = __builtin_fma(u, dx, G2);
+              G3 = __builtin_fma(u, dy, G3);
+              G4 = __builtin_fma(t3 * dy, dy, G4);
+              S3 += i3;
+            }
           }
         }
-      }
+      };
+      if (m)
+        block(std::true_type{});
+      else
+        block(std::false_type{});
       const double tt = Ee + eb;  // Neumaier across 64-charge blocks
       Ec += fabs(Ee) >= fabs(eb) ? (Ee - tt) + eb : (eb - tt) + Ee;
       Ee = tt;
@@ -716,30 +725,40 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
 //   E_i = 1/2 sum_A 1/r + sum_halo 1/r + f.d + 1/2 d.H d,  d = z_i - zr_i
 // Per patch either FP32 pairs (coordinates relative to the patch centre,
 // partials of at most 64 terms folded into FP64) or FP64 pairs.
+// SELF: the j range holds the actives, and every lane's own index lies in
+// [diag, diag + 64) (its 64-active block); only the 64-term chunks that meet
+// that range test j against the lane's index, the others need no test.
 template <bool SELF, bool WK>
 __device__ __forceinline__ void pairs32(const float* __restrict__ xs, const float* __restrict__ ys,
-                                        int b0, int b1, int self, float xf, float yf, double& G0,
-                                        double& G1, double& E, double* K, double w) {
+                                        int b0, int b1, int self, int diag, float xf, float yf,
+                                        double& G0, double& G1, double& E, double* K, double w) {
   for (int c0 = b0; c0 < b1; c0 += 64) {
     const int c1 = min(b1, c0 + 64);
     float g0 = 0.f, g1 = 0.f, e = 0.f, k0 = 0.f, k1 = 0.f, k2 = 0.f;
+    auto chunk = [&](auto self_tag) {
+      constexpr bool S = decltype(self_tag)::value;
 #pragma unroll 8
-    for (int b = c0; b < c1; ++b) {
-      const float dx = xf - xs[b], dy = yf - ys[b];
-      const float r2 = __builtin_fmaf(dx, dx, dy * dy);
-      float inv = __builtin_amdgcn_rsqf(r2);
-      if (SELF) inv = (b == self) ? 0.f : inv;
-      const float i3 = inv * inv * inv;
-      e += inv;
-      g0 = __builtin_fmaf(-dx, i3, g0);
-      g1 = __builtin_fmaf(-dy, i3, g1);
-      if (WK) {
-        const float t3 = 3.0f * i3 * inv * inv;
-        k0 += __builtin_fmaf(t3 * dx, dx, -i3);
-        k1 += t3 * dx * dy;
-        k2 += __builtin_fmaf(t3 * dy, dy, -i3);
+      for (int b = c0; b < c1; ++b) {
+        const float dx = xf - xs[b], dy = yf - ys[b];
+        const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+        float inv = __builtin_amdgcn_rsqf(r2);
+        if (S) inv = (b == self) ? 0.f : inv;
+        const float i3 = inv * inv * inv;
+        e += inv;
+        g0 = __builtin_fmaf(-dx, i3, g0);
+        g1 = __builtin_fmaf(-dy, i3, g1);
+        if (WK) {
+          const float t3 = 3.0f * i3 * inv * inv;
+          k0 += __builtin_fmaf(t3 * dx, dx, -i3);
+          k1 += t3 * dx * dy;
+          k2 += __builtin_fmaf(t3 * dy, dy, -i3);
+        }
       }
-    }
+    };
+    if (SELF && c0 < diag + 64 && c1 > diag)
+      chunk(std::true_type{});
+    else
+      chunk(std::false_type{});
     G0 += g0;
     G1 += g1;
     E += w * (double)e;
@@ -752,28 +771,35 @@ __device__ __forceinline__ void pairs32(const float* __restrict__ xs, const floa
 template <bool SELF, bool WK>
 __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
                                         const double* __restrict__ ys, int b0, int b1, int self,
-                                        double xi, double yi, double& G0, double& G1, double& E,
-                                        double& Ec, double* K, double w) {
+                                        int diag, double xi, double yi, double& G0, double& G1,
+                                        double& E, double& Ec, double* K, double w) {
   for (int c0 = b0; c0 < b1; c0 += 64) {
     const int c1 = min(b1, c0 + 64);
     double e = 0.0;
+    auto chunk = [&](auto self_tag) {
+      constexpr bool S = decltype(self_tag)::value;
 #pragma unroll 4
-    for (int b = c0; b < c1; ++b) {
-      const double dx = xi - xs[b], dy = yi - ys[b];
-      const double r2 = __builtin_fma(dx, dx, dy * dy);
-      double inv = rsqrt64(r2);
-      if (SELF) inv = (b == self) ? 0.0 : inv;
-      const double i3 = inv * inv * inv;
-      e += inv;
-      G0 = __builtin_fma(-dx, i3, G0);
-      G1 = __builtin_fma(-dy, i3, G1);
-      if (WK) {
-        const double t3 = 3.0 * i3 * inv * inv;
-        K[0] += __builtin_fma(t3 * dx, dx, -i3);
-        K[1] += t3 * dx * dy;
-        K[2] += __builtin_fma(t3 * dy, dy, -i3);
+      for (int b = c0; b < c1; ++b) {
+        const double dx = xi - xs[b], dy = yi - ys[b];
+        const double r2 = __builtin_fma(dx, dx, dy * dy);
+        double inv = rsqrt64(r2);
+        if (S) inv = (b == self) ? 0.0 : inv;
+        const double i3 = inv * inv * inv;
+        e += inv;
+        G0 = __builtin_fma(-dx, i3, G0);
+        G1 = __builtin_fma(-dy, i3, G1);
+        if (WK) {
+          const double t3 = 3.0 * i3 * inv * inv;
+          K[0] += __builtin_fma(t3 * dx, dx, -i3);
+          K[1] += t3 * dx * dy;
+          K[2] += __builtin_fma(t3 * dy, dy, -i3);
+        }
       }
-    }
+    };
+    if (SELF && c0 < diag + 64 && c1 > diag)
+      chunk(std::true_type{});
+    else
+      chunk(std::false_type{});
     const double v = w * e;
     const double tt = E + v;
     Ec += fabs(E) >= fabs(v) ? (E - tt) + v : (v - tt) + E;
@@ -814,13 +840,15 @@ __global__ __launch_bounds__(64 * MW) void k_model(RelaxDev R) {
   double G0 = 0.0, G1 = 0.0, E = 0.0, Ec = 0.0, K[3] = {0.0, 0.0, 0.0};
   if (use32) {
     const float xf = R.a32x[ac], yf = R.a32y[ac];
-    pairs32<true, WK>(R.a32x, R.a32y, a0 + j0, a0 + min(j1, na), ac, xf, yf, G0, G1, E, K, 0.5);
-    pairs32<false, WK>(R.h32x, R.h32y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, xf, yf, G0,
-                   G1, E, K, 1.0);
+    pairs32<true, WK>(R.a32x, R.a32y, a0 + j0, a0 + min(j1, na), ac, bk.y, xf, yf, G0, G1, E, K,
+                      0.5);
+    pairs32<false, WK>(R.h32x, R.h32y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, 0, xf,
+                       yf, G0, G1, E, K, 1.0);
   } else {
-    pairs64<true, WK>(R.tx, R.ty, a0 + j0, a0 + min(j1, na), ac, xi, yi, G0, G1, E, Ec, K, 0.5);
-    pairs64<false, WK>(R.h64x, R.h64y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, xi, yi, G0,
-                   G1, E, Ec, K, 1.0);
+    pairs64<true, WK>(R.tx, R.ty, a0 + j0, a0 + min(j1, na), ac, bk.y, xi, yi, G0, G1, E, Ec, K,
+                      0.5);
+    pairs64<false, WK>(R.h64x, R.h64y, h0 + max(j0, na) - na, h0 + max(j1, na) - na, -1, 0, xi,
+                       yi, G0, G1, E, Ec, K, 1.0);
   }
   part[w][0][lane] = G0;
   part[w][1][lane] = G1;
@@ -916,17 +944,29 @@ __global__ __launch_bounds__(64 * MW) void k_cg_hvp(RelaxDev R) {
   const int ac = ok ? a : a1 - 1;
   const double xi = R.zx[ac], yi = R.zy[ac];
   double Q0 = 0.0, Q1 = 0.0;
+  // in 64-term chunks: only the chunk that meets the block's own actives
+  // [bk.y, bk.y + 64) tests j against the lane's index
+  for (int c0 = a0 + j0; c0 < a0 + j1; c0 += 64) {
+    const int c1 = min(a0 + j1, c0 + 64);
+    auto chunk = [&](auto self_tag) {
+      constexpr bool S = decltype(self_tag)::value;
 #pragma unroll 4
-  for (int b = a0 + j0; b < a0 + j1; ++b) {
-    const double dx = xi - R.zx[b], dy = yi - R.zy[b];
-    const double wx = R.cwx[b], wy = R.cwy[b];
-    const double r2 = __builtin_fma(dx, dx, dy * dy);
-    double inv = rsqrt64(r2);
-    inv = (b == ac) ? 0.0 : inv;
-    const double i3 = inv * inv * inv;
-    const double sc = 3.0 * i3 * inv * inv * __builtin_fma(dx, wx, dy * wy);
-    Q0 += __builtin_fma(dx, sc, -wx * i3);
-    Q1 += __builtin_fma(dy, sc, -wy * i3);
+      for (int b = c0; b < c1; ++b) {
+        const double dx = xi - R.zx[b], dy = yi - R.zy[b];
+        const double wx = R.cwx[b], wy = R.cwy[b];
+        const double r2 = __builtin_fma(dx, dx, dy * dy);
+        double inv = rsqrt64(r2);
+        if (S) inv = (b == ac) ? 0.0 : inv;
+        const double i3 = inv * inv * inv;
+        const double sc = 3.0 * i3 * inv * inv * __builtin_fma(dx, wx, dy * wy);
+        Q0 += __builtin_fma(dx, sc, -wx * i3);
+        Q1 += __builtin_fma(dy, sc, -wy * i3);
+      }
+    };
+    if (c0 < bk.y + 64 && c1 > bk.y)
+      chunk(std::true_type{});
+    else
+      chunk(std::false_type{});
   }
   part[w][0][lane] = Q0;
   part[w][1][lane] = Q1;
