@@ -533,7 +533,7 @@ def main():
             "timing_spread": spread,
             "flops_per_pair": FLOPS_EF,
             "peak_note": ("157.3 TFLOP/s assumes packed FP32 (two FMAs per lane per instruction), "
-                          "which this build does not emit; unpacked FP32 FMA issue reaches about "
+                          "which these kernels do not use; unpacked FP32 FMA issue reaches about "
                           f"{FP32_UNPACKED_FMA_TFLOPS} TFLOP/s on gfx950 (measured issue rate)"),
             "frac_of_unpacked_fma": achieved / FP32_UNPACKED_FMA_TFLOPS,
             # each unordered pair is evaluated once, with about 17 flops of work

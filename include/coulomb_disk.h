@@ -187,18 +187,18 @@ typedef struct {
   const int32_t* boundary;   /* device int32 [n] or NULL: nonzero marks a boundary
                                 charge, pinned to the unit circle (it moves only
                                 along it); starts are projected accordingly */
-  /* Truncated-Newton polish (the benchmark spec's HVP-driven FP64 polish): below
-   * newton_tol a patch takes Newton steps -- preconditioned CG (block-Jacobi:
-   * each charge's own 2x2 Hessian block) on the tangent-space Hessian of E_sub
-   * at the current point, in optimisation coordinates (held charges: their
-   * angle, with the circle's curvature term), stopped at non-positive
-   * curvature, at a residual inf-norm of cg_eta times the gradient's (but not
-   * below gtol / 10) or after max_polish_iter iterations; then the same line
-   * search as an L-BFGS step (a failed one falls back to L-BFGS).  The
-   * Hessian products are FP64 pairs over the patch's actives plus each
-   * charge's exact block.  CD_MIXED takes one Newton step per exact
-   * expansion of the far field (from the expansion point, where the model's
-   * Hessian is the exact one); CD_FP64 takes them back to back. */
+  /* Truncated-Newton polish (FP64, driven by Hessian-vector products; Sec. II.C
+   * step 4): below newton_tol a patch takes Newton steps -- preconditioned CG
+   * (block-Jacobi: each charge's own 2x2 Hessian block) on the tangent-space
+   * Hessian of E_sub at the current point, in optimisation coordinates (held
+   * charges: their angle, with the circle's curvature term), stopped at
+   * non-positive curvature, at a residual inf-norm of cg_eta times the gradient's
+   * (but not below gtol / 10) or after max_polish_iter iterations; then the same
+   * line search as an L-BFGS step (a failed one falls back to L-BFGS).  The
+   * Hessian products are FP64 pairs over the patch's actives plus each charge's
+   * exact block.  CD_MIXED takes one Newton step per exact expansion of the far
+   * field (from the expansion point, where the model's Hessian is the exact one);
+   * CD_FP64 takes them back to back. */
   int32_t polish;            /* CD_POLISH_NEWTON, CD_POLISH_LBFGS (L-BFGS to the end) or
                                 CD_POLISH_DEFAULT: Newton on CD_FP64, L-BFGS on CD_MIXED
                                 (the faster of the two on each path) */
