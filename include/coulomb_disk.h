@@ -239,8 +239,9 @@ typedef struct {
                                 with CD_MIXED the call returns CD_ERR_INVALID_ARG);
                                 CD_EXTERIOR_MODEL: the model of CD_MIXED (explicit active and
                                 halo pairs plus the exactly re-expanded far field); with
-                                CD_FP64 its pairs are FP64 throughout, and the workspace is
-                                that of CD_MIXED */
+                                CD_FP64 its pairs are FP64 throughout, the L-BFGS history is
+                                stored in FP32 as on CD_MIXED, and the workspace is that of
+                                CD_MIXED */
 } cd_relax_opts;
 
 enum { CD_COORDS_XY = 0, CD_COORDS_TU = 1 };
