@@ -2184,6 +2184,12 @@ struct RPlan {
   double* geom;      // [3P] mixed path: proposed patch centre and radius of a halo rebuild
 };
 
+// The exact passes split the N charges into j ranges so that a pass launches
+// about kExactWaves waves (one per 64-active block and range): at 4 waves per
+// SIMD that is 16 rounds of the chip, enough to even out blocks of unequal
+// patches.  A quarter of it left a 64-patch FP64 batch 47% slower per pass.
+constexpr int kExactWaves = 65536;
+
 static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char* base, RPlan& R) {
   if (n64 < 2 || n64 > (1 << 26) || P < 1 || ntot64 < 1 || ntot64 > n64 * (int64_t)P) return false;
   if (precision != CD_FP64 && precision != CD_MIXED) return false;
@@ -2194,7 +2200,7 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   R.nbN = (R.n + 63) / 64;
   R.m = m;
   R.nblk = R.ntot / 64 + P;  // upper bound of the block table length
-  int sp = (16384 + R.nblk - 1) / R.nblk;
+  int sp = (kExactWaves + R.nblk - 1) / R.nblk;
   sp = sp < 1 ? 1 : (sp > R.nbN ? R.nbN : sp);
   R.jb = (R.nbN + sp - 1) / sp;
   R.splits = (R.nbN + R.jb - 1) / R.jb;
@@ -2204,11 +2210,12 @@ static bool rplan(int64_t n64, int P, int64_t ntot64, int precision, int m, char
   cv.base = base;
   RelaxDev& D = R.D;
   const size_t nt = R.ntot;
-  // split partials hold nt * splits values; since splits <= ceil(16384 / nblk)
-  // and nblk > nt / 64 that is below 16384 * 64 + nt, a bound that grows with
-  // nt, so the workspace of a larger batch covers every smaller one (the
-  // greedy commit sizes its scratch for the largest patch)
-  const size_t pcap = (size_t)16384 * 64 + nt;
+  // split partials hold nt * splits values; since splits <= ceil(kExactWaves /
+  // nblk), nblk > nt / 64 and splits <= nbN, that is below both
+  // kExactWaves * 64 + nt and nt * nbN, bounds that grow with nt, so the
+  // workspace of a larger batch covers every smaller one (the greedy commit
+  // sizes its scratch for the largest patch)
+  const size_t pcap = std::min((size_t)kExactWaves * 64 + nt, nt * (size_t)R.nbN);
   D.pid = cv.take<int32_t>(nt);
   D.blk = cv.take<int2>(R.nblk);
   D.maskA = cv.take<uint64_t>((size_t)P * R.nbN);
