@@ -530,6 +530,9 @@ __global__ __launch_bounds__(256) void k_exact(RelaxDev R) {
   const int p = bk.x;
   if (MODE == kGrad && !R.eval_all && (R.st[p].status != kRunning || R.st[p].phase == kPhaseCG))
     return;
+  // a re-expansion skips the patches that are finished (their far field is
+  // not used again: the final outputs come from a separate exact pass)
+  if (MODE == kFar && (R.st[p].status == kDone || R.st[p].status == kNonFinite)) return;
   // kGrad takes the Hessian blocks unless the patch's update said it can do
   // without them this time (plain path, between Newton phases); uniform per wave
   const bool wk = MODE == kFar || (MODE == kGrad && (R.eval_all || !R.st[p].skip_k));
@@ -672,7 +675,10 @@ __global__ __launch_bounds__(64 * kESW) void k_exact_sum(RelaxDev R, int mode) {
   __shared__ double part[kESW - 1][6][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a = blockIdx.x * 64 + lane;
-  const bool ok = a < R.ntot;
+  int ps = kRunning;
+  if (a < R.ntot && mode == kFar) ps = R.st[R.pid[a]].status;
+  // finished patches were left out of the re-expansion (see k_exact)
+  const bool ok = a < R.ntot && ps != kDone && ps != kNonFinite;
   // the Hessian blocks were taken for this active's patch (see k_exact)
   const bool wk = ok && (mode == kFar || (mode == kGrad && (R.eval_all || !R.st[R.pid[a]].skip_k)));
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -825,8 +831,11 @@ __global__ __launch_bounds__(64 * MW) void k_model(RelaxDev R) {
   const int2 bk = R.blk[wb];
   const int p = bk.x;
   const PState& st = R.st[p];
-  // the same for the whole workgroup; a patch in its CG phase has no trial
-  if (!R.eval_all && (st.status != kRunning || st.phase == kPhaseCG)) return;
+  // the same for the whole workgroup; a patch in its CG phase has no trial,
+  // and an evaluation at the expansion point leaves out finished patches
+  if (R.eval_all ? (st.status == kDone || st.status == kNonFinite)
+                 : (st.status != kRunning || st.phase == kPhaseCG))
+    return;
   const bool use32 = st.use32;
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
