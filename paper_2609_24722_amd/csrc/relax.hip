@@ -2074,6 +2074,13 @@ __global__ void k_copy_z_to_t(RelaxDev R) {
   R.tcu[a] = R.cu[a];
 }
 
+// Ends the round of every patch still running (its stage continues after the
+// next re-expansion, from the point it has reached).
+__global__ void k_cut(RelaxDev R) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < R.P && R.st[p].status == kRunning) R.st[p].status = kIterCap;
+}
+
 __global__ void k_count_running(RelaxDev R) {
   __shared__ int c;
   if (threadIdx.x == 0) c = 0;
@@ -2330,6 +2337,13 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
   return R.total;
 }
 
+// Mixed path: a round's stage ends for every patch once at most this percent
+// of the patches that started the round still run; the others go on from the
+// point they reached after the next re-expansion (their L-BFGS history kept),
+// alongside the rest, instead of holding the batch in rounds that run a few
+// patches on a mostly idle chip.
+constexpr int kCutPercent = 50;
+
 // Runs rounds (eval + update) until no patch is running or max rounds.
 // Returns a CD status.
 
@@ -2460,7 +2474,7 @@ static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn
 // the count reached zero find no running patch and change nothing.
 template <class EvalFn, class ShapeFn>
 static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, RoundGraphs& G,
-                      EvalFn eval, ShapeFn shape) {
+                      EvalFn eval, ShapeFn shape, int cut_at = 0) {
   RelaxDev& D = R.D;
   const int gr = R.graph_rounds;
   hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, st, D);
@@ -2511,8 +2525,10 @@ static int run_rounds(RPlan& R, hipStream_t st, int max_rounds, bool hist32, Rou
     if (hipEventSynchronize(G.cev[b]) != hipSuccess) return CD_ERR_HIP;
     R.running = G.hc[b];
     ++read;
-    if (R.running <= 0) stop = true;
+    if (R.running <= 0 || R.running <= cut_at) stop = true;
   }
+  if (R.running > 0 && R.running <= cut_at)
+    hipLaunchKernelGGL(k_cut, dim3((R.P + 255) / 256), dim3(256), 0, ls, R.D);
   const int rc = graphs ? G.end(st) : CD_OK;
   if (rc) return rc;
   return hip_status(hipGetLastError());
@@ -2802,7 +2818,8 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
       if (hr == 0) break;
       D.ptol = ptol_ws;
       rc = run_rounds(R, st, max_rounds, true, graphs,
-                      [&](hipStream_t s, int wide) { model_on(0, s, wide); }, wide_shape);
+                      [&](hipStream_t s, int wide) { model_on(0, s, wide); }, wide_shape,
+                      (int)((int64_t)hr * kCutPercent / 100));
       D.ptol = nullptr;
       if (rc) return rc;
     }
