@@ -2337,14 +2337,15 @@ size_t relax_workspace_bytes(int op, int64_t n, int32_t n_patches, int64_t total
   return R.total;
 }
 
-// Mixed path: a round's stage ends for every patch once at most this percent
-// of the patches that started the round still run; the others go on from the
-// point they reached after the next re-expansion (their L-BFGS history kept),
-// alongside the rest, instead of holding the batch in rounds that run a few
-// patches on a mostly idle chip.
+// Mixed path: once at most this percent of the patches that started a round
+// still run, their stage ends where they are (as at the iteration cap); they
+// continue it after the next re-expansion, L-BFGS history kept, alongside the
+// rest, instead of holding the batch in rounds that run a few patches on a
+// mostly idle chip.
 constexpr int kCutPercent = 50;
 
-// Runs rounds (eval + update) until no patch is running or max rounds.
+// Runs rounds (eval + update) until no patch is running or max rounds, or
+// (cut_at > 0) until at most cut_at patches run, whose rounds it then ends.
 // Returns a CD status.
 
 // Relax schedules relax_autotune chooses among (the first is the default):
