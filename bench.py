@@ -53,7 +53,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak
-FP32_UNPACKED_FMA_TFLOPS = 108.0  # unpacked v_fma_f32 issue: 5.1-5.4e13 lane-ops/s x 2 flops
+# unpacked FP32 issue: one wave64 instruction per four clocks per SIMD, 3.6-3.8e13 lane
+# instructions/s as timed by paper_2609_24722_amd/issue_rates, x 2 flops for an FMA
+FP32_UNPACKED_FMA_TFLOPS = 76.0
 FLOPS_EF = 13                # energy+forces: 2 sub, 3 r^2, 1 rsqrt, 1 add, 2 r^-3, 4 FMA
 FLOPS_EF_EXEC = 17           # executed per unordered pair: the same plus the j side's two FMAs
 FLOPS_HVP = 24
@@ -535,8 +537,9 @@ def main():
             "timing_spread": spread,
             "flops_per_pair": FLOPS_EF,
             "peak_note": ("157.3 TFLOP/s assumes packed FP32 (two FMAs per lane per instruction), "
-                          "which these kernels do not use; unpacked FP32 FMA issue reaches about "
-                          f"{FP32_UNPACKED_FMA_TFLOPS} TFLOP/s on gfx950 (measured issue rate)"),
+                          "which these kernels do not use; an all-FMA stream of unpacked FP32 "
+                          f"instructions reaches about {FP32_UNPACKED_FMA_TFLOPS} TFLOP/s on gfx950 "
+                          "(measured issue rate, one instruction per four clocks per SIMD)"),
             "frac_of_unpacked_fma": achieved / FP32_UNPACKED_FMA_TFLOPS,
             # each unordered pair is evaluated once, with about 17 flops of work
             # (2 sub, 3 r^2, rsqrt, add, 2 r^-3, 4 FMA for i, 4 FMA for j)
