@@ -1007,7 +1007,13 @@ __global__ __launch_bounds__(64 * MW) void k_cg_hvp(RelaxDev R) {
 // form the next trial point.
 constexpr int kUpd = 1024;
 constexpr int kUpdWaves = kUpd / 64;
-constexpr int kRegJ = 4;  // actives per thread held in registers by the two-loop
+// actives per thread held in registers by the two-loop: kRegJ, or kRegJWide
+// in a call with a patch above kRegJ * kUpd actives (one more register-held
+// element, so the fifth thousand of a large patch is read one step ahead like
+// the others; for smaller patches it would only add masked work).  Both
+// variants sum in the same order: the results are the same bit for bit.
+constexpr int kRegJ = 4;
+constexpr int kRegJWide = 5;
 
 // Workgroup reductions of a kUpd-thread workgroup: each wave reduces by DPP
 // (wave_sum_rows, wave_max_rows), the wave results go to LDS and every
@@ -1456,8 +1462,8 @@ __device__ void cg_iteration(RelaxDev& R, PState& s, int p, WgRed& red) {
 
 // HT: storage type of the L-BFGS history (FP32 on the mixed path, where it
 // halves the kernel's dominant memory traffic; FP64 on the plain path).  The
-// recursion itself runs in FP64.
-template <class HT, bool TU>
+// recursion itself runs in FP64.  RJ: actives per thread held in registers.
+template <class HT, bool TU, int RJ>
 __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   HT* const Sx = reinterpret_cast<HT*>(R.Sx);
   HT* const Sy = reinterpret_cast<HT*>(R.Sy);
@@ -1761,17 +1767,17 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   }
 
   // new direction: two-loop recursion on the coordinate gradient.  A
-  // thread's first kRegJ actives (a0 + t + j kUpd) keep the vector in
-  // registers; any further ones (patches above kRegJ * kUpd actives) keep it
+  // thread's first RJ actives (a0 + t + j kUpd) keep the vector in
+  // registers; any further ones (patches above RJ * kUpd actives) keep it
   // in R.dx, R.dy, touched only by their own thread, inside the same steps.
   // Each thread sums its actives in increasing order, then the workgroup sum.
   __syncthreads();
-  const int tail0 = a0 + t + kRegJ * kUpd;
-  double dxr[kRegJ], dyr[kRegJ];  // the direction of the register-held elements
+  const int tail0 = a0 + t + RJ * kUpd;
+  double dxr[RJ], dyr[RJ];  // the direction of the register-held elements
   {
-    double qx[kRegJ], qy[kRegJ];
+    double qx[RJ], qy[RJ];
 #pragma unroll
-    for (int j = 0; j < kRegJ; ++j) {
+    for (int j = 0; j < RJ; ++j) {
       const int a = a0 + t + j * kUpd;
       qx[j] = qy[j] = 0.0;
       if (a < a1) cgrad_z<TU>(R, a, R.gx[a], R.gy[a], qx[j], qy[j]);
@@ -1785,13 +1791,13 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     // FP32 history: pair k + 1 is loaded while pair k is reduced (FP64
     // history has no registers to spare for it)
     constexpr bool kPre = sizeof(HT) == 4;
-    HT ux[kRegJ], uy[kRegJ], wx[kRegJ], wy[kRegJ];
+    HT ux[RJ], uy[RJ], wx[RJ], wy[RJ];
     auto load_pair = [&](int k, HT* u0, HT* u1, HT* w0, HT* w1) {
       const bool kin = k >= 0 && k < s.mem;  // pairs outside the memory read as zero
       const int sk = s.head - 1 - (kin ? k : 0);
       const size_t base = (size_t)(sk < 0 ? sk + m : sk) * R.ntot;
 #pragma unroll
-      for (int j = 0; j < kRegJ; ++j) {
+      for (int j = 0; j < RJ; ++j) {
         const int a = a0 + t + j * kUpd;
         const bool ok = kin && a < a1;
         const size_t q = base + (size_t)min(a, a1 - 1);
@@ -1815,18 +1821,18 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       const int sk = s.head - 1 - (kin ? k : 0);
       const size_t base = (size_t)(sk < 0 ? sk + m : sk) * R.ntot;
 #pragma unroll
-      for (int j = 0; j < kRegJ; ++j) {
+      for (int j = 0; j < RJ; ++j) {
         const size_t q = base + (size_t)min(a0 + t + j * kUpd, a1 - 1);
         v0[j] = A0[q];
         v1[j] = A1[q];
       }
     };
-    double mk[kRegJ];
+    double mk[RJ];
 #pragma unroll
-    for (int j = 0; j < kRegJ; ++j) mk[j] = a0 + t + j * kUpd < a1 ? 1.0 : 0.0;
+    for (int j = 0; j < RJ; ++j) mk[j] = a0 + t + j * kUpd < a1 ? 1.0 : 0.0;
     if constexpr (kPre) {
-      HT a0s[kRegJ], a1s[kRegJ], a0y[kRegJ], a1y[kRegJ];
-      HT b0s[kRegJ], b1s[kRegJ], b0y[kRegJ], b1y[kRegJ];
+      HT a0s[RJ], a1s[RJ], a0y[RJ], a1y[RJ];
+      HT b0s[RJ], b1s[RJ], b0y[RJ], b1y[RJ];
       auto step1 = [&](int k, HT* c0s, HT* c1s, HT* c0y, HT* c1y, HT* n0s, HT* n1s, HT* n0y,
                        HT* n1y) {
         const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
@@ -1835,14 +1841,14 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         load_vec(Yx, Yy, k + 1, n0y, n1y);
         double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) v += (double)c0s[j] * qx[j] + (double)c1s[j] * qy[j];
+        for (int j = 0; j < RJ; ++j) v += (double)c0s[j] * qx[j] + (double)c1s[j] * qy[j];
         for (int a = tail0; a < a1; a += kUpd)
           v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
         const double rk = s_rho[kk];  // read ahead of the reduction's barrier
         const double al = rk * block_sum(v, red);
         if (t == 0) s_alf[kk] = al;
 #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) {
+        for (int j = 0; j < RJ; ++j) {
           qx[j] -= al * (mk[j] * (double)c0y[j]);
           qy[j] -= al * (mk[j] * (double)c1y[j]);
         }
@@ -1862,21 +1868,21 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       for (int k = 0; k < s.mem; ++k) {
         const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
         const size_t base = (size_t)kk * R.ntot;
-        HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+        HT nux[RJ], nuy[RJ], nwx[RJ], nwy[RJ];
         if (kPre)
           load_pair(k + 1, nux, nuy, nwx, nwy);
         else
           load_pair(k, ux, uy, wx, wy);
         double v = 0.0;
   #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
+        for (int j = 0; j < RJ; ++j) v += (double)ux[j] * qx[j] + (double)uy[j] * qy[j];
         for (int a = tail0; a < a1; a += kUpd)
           v += (double)Sx[base + a] * R.dx[a] + (double)Sy[base + a] * R.dy[a];
         const double rk = s_rho[kk];  // read ahead of the reduction's barrier
         const double al = rk * block_sum(v, red);
         if (t == 0) s_alf[kk] = al;
   #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) {
+        for (int j = 0; j < RJ; ++j) {
           qx[j] -= al * (double)wx[j];
           qy[j] -= al * (double)wy[j];
           if (kPre) {
@@ -1895,7 +1901,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     // the preconditioner, in registers for the register-held elements and
     // in memory for the tail
 #pragma unroll
-    for (int j = 0; j < kRegJ; ++j) {
+    for (int j = 0; j < RJ; ++j) {
       const int a = a0 + t + j * kUpd;
       if (a < a1) {
         double r0, r1;
@@ -1911,8 +1917,8 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       R.dy[a] = r1;
     }
     if constexpr (kPre) {
-      HT a0s[kRegJ], a1s[kRegJ], a0y[kRegJ], a1y[kRegJ];
-      HT b0s[kRegJ], b1s[kRegJ], b0y[kRegJ], b1y[kRegJ];
+      HT a0s[RJ], a1s[RJ], a0y[RJ], a1y[RJ];
+      HT b0s[RJ], b1s[RJ], b0y[RJ], b1y[RJ];
       auto step2 = [&](int k, HT* c0s, HT* c1s, HT* c0y, HT* c1y, HT* n0s, HT* n1s, HT* n0y,
                        HT* n1y) {
         const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
@@ -1921,14 +1927,14 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
         load_vec(Yx, Yy, k - 1, n0y, n1y);
         double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) v += (double)c0y[j] * qx[j] + (double)c1y[j] * qy[j];
+        for (int j = 0; j < RJ; ++j) v += (double)c0y[j] * qx[j] + (double)c1y[j] * qy[j];
         for (int a = tail0; a < a1; a += kUpd)
           v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
         const double rk = s_rho[kk];
         const double be = rk * block_sum(v, red);
         const double coef = s_alf[kk] - be;
 #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) {
+        for (int j = 0; j < RJ; ++j) {
           qx[j] += coef * (mk[j] * (double)c0s[j]);
           qy[j] += coef * (mk[j] * (double)c1s[j]);
         }
@@ -1948,21 +1954,21 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       for (int k = s.mem - 1; k >= 0; --k) {
         const int kk = s.head - 1 - k < 0 ? s.head - 1 - k + m : s.head - 1 - k;
         const size_t base = (size_t)kk * R.ntot;
-        HT nux[kRegJ], nuy[kRegJ], nwx[kRegJ], nwy[kRegJ];
+        HT nux[RJ], nuy[RJ], nwx[RJ], nwy[RJ];
         if (kPre)
           load_pair(k - 1, nux, nuy, nwx, nwy);
         else
           load_pair(k, ux, uy, wx, wy);
         double v = 0.0;
   #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
+        for (int j = 0; j < RJ; ++j) v += (double)wx[j] * qx[j] + (double)wy[j] * qy[j];
         for (int a = tail0; a < a1; a += kUpd)
           v += (double)Yx[base + a] * R.dx[a] + (double)Yy[base + a] * R.dy[a];
         const double rk = s_rho[kk];
         const double be = rk * block_sum(v, red);
         const double coef = s_alf[kk] - be;
   #pragma unroll
-        for (int j = 0; j < kRegJ; ++j) {
+        for (int j = 0; j < RJ; ++j) {
           qx[j] += coef * (double)ux[j];
           qy[j] += coef * (double)uy[j];
           if (kPre) {
@@ -1979,7 +1985,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
       }
     }
 #pragma unroll
-    for (int j = 0; j < kRegJ; ++j) {
+    for (int j = 0; j < RJ; ++j) {
       dxr[j] = qx[j];
       dyr[j] = qy[j];
     }
@@ -1990,7 +1996,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   // the tail: the actives in increasing order, as everywhere.
   double dg = 0.0, dm = 0.0;
 #pragma unroll
-  for (int j = 0; j < kRegJ; ++j) {
+  for (int j = 0; j < RJ; ++j) {
     const int a = a0 + t + j * kUpd;
     if (a < a1) {
       double c0, c1;
@@ -2025,7 +2031,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
     }
     dm = block_max(dm, red);
 #pragma unroll
-    for (int j = 0; j < kRegJ; ++j) {
+    for (int j = 0; j < RJ; ++j) {
       const int a = a0 + t + j * kUpd;
       if (a < a1) {
         dxr[j] = R.dx[a];
@@ -2036,7 +2042,7 @@ __global__ __launch_bounds__(kUpd) void k_update(RelaxDev R) {
   const double sc = dm > R.step0 ? R.step0 / dm : 1.0;
   s.alpha = 1.0;
 #pragma unroll
-  for (int j = 0; j < kRegJ; ++j) {
+  for (int j = 0; j < RJ; ++j) {
     const int a = a0 + t + j * kUpd;
     if (a < a1) set_trial<TU>(R, s, a, dxr[j] * sc, dyr[j] * sc);
   }
@@ -2193,6 +2199,7 @@ struct RPlan {
   int graph_rounds = 8;
   int64_t wide_blocks = 512;
   bool use_graphs = true;  // rounds replayed from HIP graphs (else launched one by one)
+  int regj = kRegJ;        // actives per thread in registers in the update (kRegJ or kRegJWide)
   size_t total;
   RelaxDev D;
   int32_t* hcount;  // [P]
@@ -2441,6 +2448,18 @@ struct RoundGraphs {
   }
 };
 
+template <int RJ>
+static void launch_update(RPlan& R, hipStream_t s, bool hist32) {
+  if (hist32 && R.D.tu)
+    hipLaunchKernelGGL((k_update<float, true, RJ>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else if (hist32)
+    hipLaunchKernelGGL((k_update<float, false, RJ>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else if (R.D.tu)
+    hipLaunchKernelGGL((k_update<double, true, RJ>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  else
+    hipLaunchKernelGGL((k_update<double, false, RJ>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+}
+
 template <class EvalFn>
 static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn& eval) {
   if (R.D.polish) {  // CG iterations of patches in a Newton step, then the trial evaluations
@@ -2452,14 +2471,10 @@ static void launch_round(RPlan& R, hipStream_t s, bool hist32, int shape, EvalFn
   eval(s, shape);
   // the (t, u) variant only when the call asked for it: the (x, y) kernel
   // carries none of its branches
-  if (hist32 && R.D.tu)
-    hipLaunchKernelGGL((k_update<float, true>), dim3(R.P), dim3(kUpd), 0, s, R.D);
-  else if (hist32)
-    hipLaunchKernelGGL((k_update<float, false>), dim3(R.P), dim3(kUpd), 0, s, R.D);
-  else if (R.D.tu)
-    hipLaunchKernelGGL((k_update<double, true>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+  if (R.regj == kRegJWide)
+    launch_update<kRegJWide>(R, s, hist32);
   else
-    hipLaunchKernelGGL((k_update<double, false>), dim3(R.P), dim3(kUpd), 0, s, R.D);
+    launch_update<kRegJ>(R, s, hist32);
 }
 
 // eval(stream, shape) enqueues one evaluation; shape(): 0 or 1, the
@@ -2674,9 +2689,13 @@ int relax_subdomains(const double* x, const double* y, int64_t n, int32_t n_patc
 
   std::vector<int2> blk;
   blk.reserve(R.nblk);
-  for (int p = 0; p < n_patches; ++p)
+  int max_na = 0;
+  for (int p = 0; p < n_patches; ++p) {
+    max_na = std::max(max_na, patch_ptr[p + 1] - patch_ptr[p]);
     for (int a = patch_ptr[p]; a < patch_ptr[p + 1]; a += 64) blk.push_back(make_int2(p, a));
+  }
   D.nblk = (int)blk.size();
+  R.regj = max_na > kRegJ * kUpd ? kRegJWide : kRegJ;
   int rc;
   if ((rc = hip_status(hipMemcpyAsync(D.ptr_w, patch_ptr, sizeof(int32_t) * (n_patches + 1),
                                       hipMemcpyHostToDevice, st))))

@@ -144,14 +144,15 @@ def test_same_basin_energy_parity(dev):
 
 
 def test_large_patch_same_basin(dev):
-    # a patch of 4500 actives (above the update kernel's register capacity of
-    # 4096, so its two-loop runs through memory) beside a small one: from a
-    # common near-minimum start both paths reach the same minimum
+    # a patch of 5600 actives (above the update kernel's register capacity,
+    # 5 x 1024 in a call with a patch above 4096, so part of its two-loop runs
+    # through memory) beside a small one: from a common near-minimum start both
+    # paths reach the same minimum
     n = 20000
     x, y = W.warped_lattice(n, 0.05, 21)
     h = W.spacing(n)
     centres = np.array([17, 15000], dtype=np.int32)
-    sizes = np.array([4500, 300], dtype=np.int32)
+    sizes = np.array([5600, 300], dtype=np.int32)
     xt, yt = t(x, dev), t(y, dev)
     ptr, idx = R.build_patches(xt, yt, centres, sizes)
     idx_np = idx.cpu().numpy()
