@@ -1009,9 +1009,10 @@ constexpr int kUpd = 1024;
 constexpr int kUpdWaves = kUpd / 64;
 // actives per thread held in registers by the two-loop: kRegJ, or kRegJWide
 // in a call with a patch above kRegJ * kUpd actives (one more register-held
-// element, so the fifth thousand of a large patch is read one step ahead like
-// the others; for smaller patches it would only add masked work).  Both
-// variants sum in the same order: the results are the same bit for bit.
+// element per thread, so that a large patch's actives 4097 to 5120 are loaded
+// one step ahead like the others instead of inside each step; for smaller
+// patches it would only add masked work).  Both variants sum in the same
+// order: the results are the same bit for bit.
 constexpr int kRegJ = 4;
 constexpr int kRegJWide = 5;
 
