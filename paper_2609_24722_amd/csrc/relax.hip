@@ -814,9 +814,10 @@ __device__ __forceinline__ void pairs64(const double* __restrict__ xs,
 }
 
 // One workgroup per 64-active block; its MW waves split the patch's j list
-// (actives, then halo) into ranges cut at multiples of 64 and the partial
-// sums are combined in LDS in wave order, so a large patch spreads over
-// MW times more waves.  MW = kMW, or kMWWide when few blocks belong to
+// (actives, then halo) into ranges cut at multiples of 16 (at multiples of
+// 64 the last waves of a workgroup often had little or nothing to do while
+// the others set its time) and the partial sums are combined in LDS in wave
+// order, so a large patch spreads over MW times more waves.  MW = kMW, or kMWWide when few blocks belong to
 // patches still running (the chip would otherwise sit mostly idle).
 constexpr int kMW = 8;
 constexpr int kMWWide = 16;
@@ -840,7 +841,7 @@ __global__ __launch_bounds__(64 * MW) void k_model(RelaxDev R) {
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int h0 = R.hptr[p], h1 = R.hptr[p + 1];
   const int na = a1 - a0, nj = na + (h1 - h0);
-  const int per = ((nj + MW - 1) / MW + 63) & ~63;
+  const int per = ((nj + MW - 1) / MW + 15) & ~15;
   const int j0 = min(nj, w * per), j1 = min(nj, j0 + per);
   const int a = bk.y + lane;
   const bool ok = a < a1;
