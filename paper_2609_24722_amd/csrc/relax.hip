@@ -933,7 +933,7 @@ __global__ void k_model_prep(RelaxDev R, int halo_too) {
 // angle, with tangent t = (-y, x): its component is t . (H w)_i - (g_i . z_i)
 // d_i (the circle's curvature), a free charge's (H w)_i.  FP64 pairs.
 // Workgroup layout as k_model: MW waves split the patch's actives into
-// ranges cut at multiples of 64; their sums are combined in wave order.
+// ranges cut at multiples of 16; their sums are combined in wave order.
 template <int MW>
 __global__ __launch_bounds__(64 * MW) void k_cg_hvp(RelaxDev R) {
   __shared__ double part[MW][2][64];
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(64 * MW) void k_cg_hvp(RelaxDev R) {
   if (st.status != kRunning || st.phase != kPhaseCG) return;  // uniform in the workgroup
   const int a0 = R.ptr[p], a1 = R.ptr[p + 1];
   const int na = a1 - a0;
-  const int per = ((na + MW - 1) / MW + 63) & ~63;
+  const int per = ((na + MW - 1) / MW + 15) & ~15;
   const int j0 = min(na, w * per), j1 = min(na, j0 + per);
   const int a = bk.y + lane;
   const bool ok = a < a1;
