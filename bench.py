@@ -34,12 +34,13 @@ times one relax call on the 256 patches of workload 4; --defect-only mixed|fp64
 runs one defect-targeted cycle; --border-sweep N runs one such cycle per
 boundary population around Eq. 4 under the border-interior split (Sec. II.B);
 --copy-probe runs a plain device copy of known size (to calibrate HBM byte
-counters).
+counters); --pair-scaling N1,N2,... times the mixed energy+forces call at each N.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
                        [--no-relax] [--tune] [--cycles K --cycle-n N --cycle-precision P]
                        [--relax-only mixed|fp64] [--defect-only mixed|fp64 --defect-T T
                        --defect-kappa K] [--no-defect] [--border-sweep N] [--copy-probe]
+                       [--pair-scaling N1,N2,...]
 """
 import argparse
 import ctypes
@@ -404,6 +405,29 @@ def border_sweep(dev, n, T, precision, offsets=(-2, -1, 0, 1, 2)):
                       "precision": "mixed" if precision else "fp64"}), flush=True)
 
 
+def pair_scaling(dev, sizes, lib, hip):
+    """The mixed energy+forces call on the warped lattice at each N: call and
+    pair-kernel times (the kernel interval spans every batch of partial sums
+    and their reductions where one call needs several), pair rate and the
+    roofline fraction of 13 flops per ordered pair."""
+    import torch
+    from paper_2609_24722_amd import MIXED, ops
+    from paper_2609_24722_amd import workloads as W
+    for n in sizes:
+        x, y = W.workload(3, n)
+        xt = torch.tensor(x, device=dev)
+        yt = torch.tensor(y, device=dev)
+        steps = 5 if n > 200000 else 20
+        call_ms, kern_ms = timed(lambda: ops.forces(xt, yt, MIXED), steps, 2, lib, hip)
+        pairs = x.size * (x.size - 1)
+        print(json.dumps({"n": x.size, "call_ms": call_ms, "kernel_ms": kern_ms,
+                          "pairs_per_s": pairs / (call_ms * 1e-3),
+                          "frac": FLOPS_EF * pairs / (kern_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}),
+              flush=True)
+        del xt, yt
+        torch.cuda.empty_cache()
+
+
 def traffic_from_profiles():
     """HBM bytes per launch of the pair kernel from the committed counter
     summary, if it matches the current kernel build; else None."""
@@ -450,6 +474,9 @@ def main():
     ap.add_argument("--tune-relax", action="store_true",
                     help="pick relax schedules with relax_autotune (workload 4, and per batch size class "
                          "in an untimed warm-up cycle) before the relax and cycle measurements")
+    ap.add_argument("--pair-scaling", type=str, default=None,
+                    help="comma-separated N: time the mixed energy+forces call at each N "
+                         "(20 timed calls after 2 warm-ups, 5 above N = 2e5), one JSON line per N")
     ap.add_argument("--relax-only", choices=["mixed", "fp64"], default=None,
                     help="time one relax_subdomains call on the 256 patches of workload 4 and exit")
     args = ap.parse_args()
@@ -484,6 +511,9 @@ def main():
     lib.coulomb_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.coulomb_set_kernel_events.restype = None
     hip = hip_runtime()
+    if args.pair_scaling:
+        pair_scaling(dev, [int(float(v)) for v in args.pair_scaling.split(",")], lib, hip)
+        return
 
     x, y = W.workload(3, args.n)
     n = x.size
